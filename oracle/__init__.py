@@ -1,0 +1,25 @@
+"""FP64 CPU oracle for hard-coded-gradient GRAPE.  TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke entry point and the benchmark's CPU-baseline leg
+may import this package.  The GPU product path never calls into it, and it
+shares no code with the HIP library: no kernels, headers, helpers or constants.
+
+Modules
+  grape    exact cost and gradient: dense Pade expm per step, all states
+           stored, co-state recursion, Frechet derivative of expm
+           (Van Loan block, or Daleckii-Krein in the eigenbasis)
+  planner  the paper's error bound E_A(m, s) and its (m, s) selection rule
+  taylor   the paper's Taylor scaling-and-squaring action and the auxiliary
+           block-matrix derivative action, written plainly in FP64
+
+Every function cites the passage of Lu, Joshi, Dinh, Koch,
+"Optimal control of large quantum systems: assessing memory and runtime
+performance of GRAPE" (arXiv:2304.06200) that it follows.
+
+Parity status: grape and taylor are pinned by closed forms, invariants, finite
+differences and high-precision references (tests/test_oracle_*.py).  The
+planner formula is pinned by closed forms of its s=1 and s=2 special cases and
+by the empirical bound property; *which* (m, s) the authors obtained for any
+given norm is parity unpinned (the paper prints no such values).
+"""
+from . import grape, planner, taylor  # noqa: F401
