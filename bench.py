@@ -1,0 +1,158 @@
+"""Benchmark: HG-GRAPE cost+gradient evaluations per second on one MI355X.
+
+Workload: the d = 1600 transmon(4) x transmon(4) x cavity(100) problem with six
+controls, N = 2000 steps of 0.5 ns, 16 initial states, forbidden-level
+penalty, synthetic seeded amplitudes.  One "step" of this benchmark is one
+batched call that evaluates cost and full gradient for --batch independent
+amplitude sets (the concurrency that fills the GPU: one workgroup per state
+column).  The reported value is whole-job throughput in complex64; complex128
+is measured the same way and reported beside it.
+
+    python bench.py [--steps K] [--warmup W] [--batch B] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cost+gradient evals/s (dim 1600, N=2000, 16 states) c64 vs c128; p99 ms served"
+PEAK_VALU_TFLOPS = 78.6  # unpacked FP32 FMA and FP64 FMA: 256 CU x 64 lanes x 2 flop x 2.4 GHz
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def flops_per_term(nnz, nnz_ctrl, K):
+    """Algorithmic flops of one Taylor term for one state column (8 per complex MAC)."""
+    fwd = 8.0 * nnz
+    bwd = 8.0 * ((3 + K) * nnz + sum(nnz_ctrl))  # psi, Lambda, Y, X_1..X_K, E_k products
+    return fwd, bwd
+
+
+def run_precision(hg, prob, u, psi0, tg, p, dtype, steps, warmup):
+    import numpy as np
+    import torch
+    kw = dict(w_fid=p.w_fid, w_pen=p.w_pen, tau=p.tau, dtype=dtype, timing=True)
+    for w in range(warmup):
+        hg.evaluate(prob, u, psi0, tg, p.dt, **kw)
+        log(f"  warmup {w + 1}/{warmup} {dtype} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fw, bw, res = [], [], None
+    for s in range(steps):
+        res = hg.evaluate(prob, u, psi0, tg, p.dt, **kw)
+        fw.append(res.ms_forward)
+        bw.append(res.ms_backward)
+        log(f"  step {s + 1}/{steps} {dtype}: fwd {res.ms_forward:.1f} ms bwd {res.ms_backward:.1f} ms")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"seconds": el, "ms_per_step": 1000.0 * el / steps, "ms_forward": float(np.mean(fw)),
+            "ms_backward": float(np.mean(bw)), "sum_mu": res.sum_mu, "cost": res.cost,
+            "drift": float(np.max(res.drift))}
+
+
+def cpu_baseline(p_full, n_sample):
+    """The FP64 oracle on the first n_sample steps of the same workload (all
+    states), scaled to one full evaluation."""
+    import numpy as np
+    from oracle import grape
+    from workloads import make_config
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    p = make_config("cfg3", N=n_sample)
+    t0 = time.perf_counter()
+    grape.cost_and_grad(p.H0, p.Hk, p.u, p.dt, p.psi0, p.targets, omega=p.omega,
+                        w_fid=p.w_fid, w_pen=p.w_pen)
+    el = time.perf_counter() - t0
+    per_eval = el * p_full.n_steps / n_sample
+    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_sample} of {p_full.n_steps} steps, all {p_full.n_states} states, "
+                      f"d={p_full.dim} ({el:.1f} s), scaled x{p_full.n_steps // n_sample}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c128", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the evaluation is a "
+              f"single-GPU path; see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2304_06200_amd as hg
+    from workloads import make_config
+    from workloads.configs import _amps
+
+    p = make_config("cfg3")
+    B = args.batch
+    us = np.stack([p.u] + [_amps(np.random.default_rng(100 + b), p.n_ctrl, p.n_steps)
+                           for b in range(1, B)])
+    log(f"[bench] cfg3 d={p.dim} N={p.n_steps} S={p.n_states} K={p.n_ctrl} batch={B}")
+    ctx = hg.Context(0)
+    prob = hg.Problem(ctx, p.H0, p.Hk, p.omega)
+    u = torch.tensor(us, dtype=torch.float64, device="cuda")
+    psi0 = torch.tensor(p.psi0, dtype=torch.complex128, device="cuda")
+    tg = torch.tensor(p.targets, dtype=torch.complex128, device="cuda")
+    nnz = prob.info["nnz"]
+    nnz_ctrl = [int(h.nnz) for h in p.Hk]
+    fpt_f, fpt_b = flops_per_term(nnz, nnz_ctrl, p.n_ctrl)
+
+    out = {}
+    for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
+        log(f"[bench] {dtype}")
+        r = run_precision(hg, prob, u, psi0, tg, p, dtype, args.steps, args.warmup)
+        terms = float(np.sum(r["sum_mu"])) * p.n_states   # Taylor terms x columns, whole batch
+        r["tflops_backward"] = fpt_b * terms / (r["ms_backward"] * 1e-3) / 1e12
+        r["tflops_forward"] = fpt_f * terms / (r["ms_forward"] * 1e-3) / 1e12
+        r["evals_per_s"] = B / (r["ms_per_step"] * 1e-3)
+        out[dtype] = r
+        log(f"[bench] {dtype}: {r['evals_per_s']:.3f} evals/s, backward {r['tflops_backward']:.2f} "
+            f"TFLOP/s, forward {r['tflops_forward']:.2f} TFLOP/s")
+
+    main_r = out["c64"]
+    line = {
+        "metric": METRIC, "value": main_r["evals_per_s"], "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "cfg3: transmon(4) x transmon(4) x cavity(100), d=1600, K=6, "
+                               "N=2000, dt=0.5 ns, S=16, penalty on",
+                   "concurrent_evals": B, "tau": p.tau, "precision": "c64 (FP64 norms, "
+                   "planner, overlaps, reductions)",
+                   "sum_mu_per_eval": int(np.mean(main_r["sum_mu"]))},
+        "roofline": {"bound": "alu", "kernel": "hg_backward", "achieved": main_r["tflops_backward"],
+                     "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": main_r["tflops_backward"] / PEAK_VALU_TFLOPS, "traffic": None},
+    }
+    if "c128" in out:
+        c = out["c128"]
+        line["c128"] = {"value": c["evals_per_s"], "unit": "evals/s", "ms_per_step": c["ms_per_step"],
+                        "roofline_frac_backward": c["tflops_backward"] / PEAK_VALU_TFLOPS,
+                        "tflops_backward": c["tflops_backward"]}
+        line["c64_over_c128"] = main_r["evals_per_s"] / c["evals_per_s"]
+    line["kernel_ms"] = {d: {"forward": out[d]["ms_forward"], "backward": out[d]["ms_backward"]}
+                         for d in out}
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle on {args.cpu_sample} steps")
+        line["cpu_baseline"] = cpu_baseline(p, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

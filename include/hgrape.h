@@ -1,0 +1,178 @@
+/*
+ * hgrape.h -- C ABI of the hard-coded-gradient (HG) GRAPE cost+gradient
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Lu, Joshi, Dinh, Koch, "Optimal control of large quantum systems:
+ * assessing memory and runtime performance of GRAPE", arXiv:2304.06200.
+ *
+ *   H_n   = H_0 + sum_k u[k][n] H_k,  piecewise constant over N steps of dt
+ *           (Sec. II; several control channels as in its footnote)
+ *   psi_n = exp(-i H_n dt) psi_{n-1}   approximated by (T_m(B_n))^s psi_{n-1},
+ *           B_n = -i dt H_n / s, T_m(B) = sum_{q<=m} B^q/q!  (Sec. III.B)
+ *   (m_n, s_n): smallest s, then smallest m, with E_A(m, s) <= tau
+ *           (Sec. III.B rule, App. C bound; ||A_n||_1 computed exactly in FP64)
+ *   cost  C = w_fid (1 - |g|^2) + w_pen C2,
+ *           g  = (1/S) sum_h <phi_T^h|psi_N^h>       (Sec. III.A, C1^st / C1^g)
+ *           C2 = 1/(N S) sum_h sum_{n=1..N} <psi_n^h|Omega|psi_n^h>   (App. A, C2^st)
+ *   grad  dC/du[k][n] = 2 Re sum_h <Lambda_n^h| dU_n/du_k |psi_{n-1}^h>
+ *           (Sec. III.A eqs. stgradient/gategradient, App. A eq. C2stgrad),
+ *           dU_n/du_k psi by the auxiliary block matrix [[A, E_k],[0, A]]
+ *           (Sec. III.B, eq. auxiliary equation), with the forward-backward
+ *           sweep of Sec. III.C: states are rebuilt backwards by inverse
+ *           propagation, nothing per time step is stored.
+ *
+ * Conventions
+ *   - Every function returns hg_status; no exception crosses the ABI.  On an
+ *     error, hg_last_error() returns a thread-local message with the detail.
+ *   - Complex numbers are interleaved (re, im) pairs of doubles at the ABI.
+ *   - A state block is [S][dim]: state h occupies dim consecutive complex
+ *     numbers.  Batched arrays add a leading [n_batch] dimension.
+ *   - hg_eval_desc arrays are DEVICE pointers (memory of the context's
+ *     device, e.g. from hipMalloc or a torch tensor), except where a field
+ *     says "host".  Results' scalar fields are host memory; grad is device.
+ *   - The library never takes ownership of caller memory.  Operators are
+ *     copied to the device at hg_problem_create.
+ *   - Thread safety: a problem is immutable after creation and may be used
+ *     by concurrent hg_eval calls on different streams.  A context may be
+ *     used from several threads.
+ */
+#ifndef HGRAPE_H
+#define HGRAPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HG_OK = 0,
+  HG_ERR_INVALID_ARG = 1,           /* bad size, pointer, flag or unnormalised psi0 */
+  HG_ERR_NOT_HERMITIAN = 2,         /* H_0 or some H_k is not Hermitian to 1e-12 relative */
+  HG_ERR_NONFINITE = 3,             /* NaN/Inf in operators, amplitudes or dt */
+  HG_ERR_TOLERANCE_UNREACHABLE = 4, /* no (m, s) meets E_A <= tau for some step */
+  HG_ERR_OUT_OF_MEMORY = 5,         /* device allocation failed / over budget */
+  HG_ERR_DEVICE = 6,                /* a HIP runtime call failed */
+  HG_ERR_BUSY = 7,                  /* server queue full */
+  HG_ERR_CANCELLED = 8,             /* request cancelled before it ran */
+  HG_ERR_UNSUPPORTED = 9            /* shape outside what the kernels are built for */
+} hg_status;
+
+typedef enum { HG_C64 = 0, HG_C128 = 1 } hg_dtype;  /* arithmetic of the Taylor products */
+typedef enum { HG_MODE_RECONSTRUCT = 0, HG_MODE_CHECKPOINT = 1 } hg_mode;
+
+/* A host CSR matrix of complex128 values (dim x dim). */
+typedef struct {
+  int64_t n;                 /* number of rows (= dim) */
+  const int64_t* indptr;     /* host, [n + 1] */
+  const int32_t* indices;    /* host, [indptr[n]], column indices in [0, n) */
+  const double* values;      /* host, [2 * indptr[n]] interleaved complex128 */
+} hg_csr;
+
+typedef struct hg_ctx hg_ctx;
+typedef struct hg_problem hg_problem;
+
+/* Create a context bound to HIP device `device_ordinal`. */
+hg_status hg_create(int device_ordinal, hg_ctx** out);
+hg_status hg_destroy(hg_ctx* ctx);
+const char* hg_status_string(hg_status s);
+const char* hg_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t hg_version(void);
+
+/* Build a problem: drift H0, n_ctrl control operators Hk[k] (all dim x dim,
+ * Hermitian) and an optional diagonal penalty operator Omega (host [dim]
+ * real, or NULL for no penalty).  The union sparsity pattern of H0 and all
+ * Hk is stored on the device by diagonals (DIA: one value per row and union
+ * diagonal, zero outside the matrix), each operator's values on it; each Hk
+ * also gets its own diagonals for the derivative products.  Duplicate CSR
+ * entries are summed, explicit zeros dropped.
+ * Errors: INVALID_ARG (bad CSR, dim < 1, n_ctrl < 0), NOT_HERMITIAN,
+ * NONFINITE, UNSUPPORTED (more than 13 union diagonals, more than 4 diagonals
+ * in one control, dim > 4096, n_ctrl > 16), DEVICE. */
+hg_status hg_problem_create(hg_ctx* ctx, int64_t dim, int32_t n_ctrl,
+                            const hg_csr* H0, const hg_csr* Hk,
+                            const double* omega_diag, hg_problem** out);
+hg_status hg_problem_destroy(hg_problem* p);
+
+/* Problem facts: dim, n_ctrl, number of union diagonals, sigma' (the
+ * largest number of non-zeros in a row of the union pattern, App. C eq.
+ * sigmapdef) and the number of stored union non-zeros.  Any pointer may be NULL. */
+hg_status hg_problem_info(const hg_problem* p, int64_t* dim, int32_t* n_ctrl,
+                          int32_t* ell_width, int32_t* sigma, int64_t* nnz);
+
+/* Host planner (Sec. III.B rule, App. C bound), FP64.  For each of n norms
+ * theta[i] = ||A_i||_1 (host) choose the smallest s, then the smallest
+ * m in [1, 60], with E_A(m, s) <= tau, using unit roundoff u (2^-53 for FP64
+ * arithmetic).  Writes m_out[i], s_out[i] (host).  Errors: INVALID_ARG,
+ * NONFINITE (theta not finite), TOLERANCE_UNREACHABLE (the first failing
+ * index and the bound's floor are in hg_last_error()). */
+hg_status hg_plan(const double* theta, int64_t n, int32_t sigma, double tau, double u,
+                  int32_t* m_out, int32_t* s_out);
+
+/* Error bound E_A(m, s) of App. C at ||A||_1 = theta (host, FP64). */
+double hg_error_bound(double theta, int32_t m, int32_t s, int32_t sigma, double u);
+
+/* Exact per-step 1-norms theta[b][n] = dt * max_i sum_j |(H_0 + sum_k u[b][k][n] H_k)_ij|
+ * (App. C, eq. norm inequality) for n_batch amplitude sets, FP64, on `stream`
+ * (a hipStream_t, NULL = default).  u: device [n_batch][n_ctrl][n_steps];
+ * theta_out: device [n_batch][n_steps].  Asynchronous. */
+hg_status hg_step_norms(hg_problem* p, const double* u, int32_t n_batch, int32_t n_steps,
+                        double dt, double* theta_out, void* stream);
+
+typedef struct {
+  int32_t n_steps;           /* N >= 1 */
+  int32_t n_batch;           /* B >= 1 independent evaluations of this problem */
+  double dt;                 /* step length (ns; H in rad/ns, hbar = 1) */
+  const double* u;           /* device [B][n_ctrl][N] amplitudes, FP64 */
+  int32_t n_states;          /* S >= 1 */
+  const double* psi0;        /* device [B][S][dim] complex128, each column normalised */
+  const double* targets;     /* device [B][S][dim] complex128 target states phi_T^h */
+  double w_fid, w_pen;       /* cost weights alpha_nu (Sec. II); w_pen ignored without Omega */
+  double tau;                /* per-step tolerance of the Taylor action (Sec. III.B) */
+  hg_dtype dtype;            /* arithmetic of the state products (norms, planner,
+                                overlaps and reductions are FP64 in both) */
+  hg_mode mode;              /* RECONSTRUCT (HG inverse propagation) or CHECKPOINT */
+  int32_t ckpt_every;        /* CHECKPOINT: store psi every C steps (C >= 1) */
+  int32_t renorm_every;      /* rescale psi to unit norm every R steps (0 = never);
+                                applied to the forward and reconstructed states */
+  const int32_t* schedule;   /* NULL, or host [2][B][N]: frozen (m, s) per step
+                                (the planner is skipped; norms are still computed) */
+  int32_t flags;             /* bit 0 (HG_FLAG_TIMING): time the sweep kernels with
+                                HIP events on `stream`, reported in hg_result */
+} hg_eval_desc;
+
+#define HG_FLAG_TIMING 1
+
+typedef struct {
+  double cost;               /* w_fid * infidelity + w_pen * penalty */
+  double infidelity;         /* C1 = 1 - |g|^2 */
+  double penalty;            /* C2 */
+  double overlap_re, overlap_im;  /* g */
+  int64_t sum_mu;            /* sum over steps of m_n s_n */
+  double max_theta;          /* max_n ||A_n||_1 */
+  double max_bound;          /* max_n E_A(m_n, s_n) (0 with a frozen schedule) */
+  double drift;              /* reconstruction drift: max_h ||psi_0^h(rebuilt) - psi_0^h|| */
+  double ms_forward;         /* with HG_FLAG_TIMING: forward-sweep kernel time (whole batch) */
+  double ms_backward;        /* with HG_FLAG_TIMING: backward-sweep kernel time (whole batch) */
+} hg_result;
+
+/* Evaluate cost and gradient for B amplitude sets.  results: host [B];
+ * grad: device [B][n_ctrl][N] FP64 (may be NULL for cost only).  Work is
+ * enqueued on `stream`; the call returns after the stream has finished it
+ * (the planner needs the norms on the host mid-way), so results and grad
+ * are valid on return.  Errors: INVALID_ARG, NONFINITE, TOLERANCE_UNREACHABLE,
+ * UNSUPPORTED, OUT_OF_MEMORY, DEVICE. */
+hg_status hg_eval(hg_problem* p, const hg_eval_desc* desc, hg_result* results,
+                  double* grad, void* stream);
+
+/* Device memory the library would allocate for one hg_eval call with this
+ * shape (workspace only; caller buffers excluded).  Used for admission. */
+hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* desc, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGRAPE_H */

@@ -1,0 +1,12 @@
+"""Hard-coded-gradient GRAPE cost+gradient on AMD MI355X (gfx950).
+
+The product path is libhgrape.so (HIP kernels + C++ host planner) behind the C
+ABI declared in include/hgrape.h.  Python provides the ctypes binding
+(``_lib``, same names as the C functions), a thin torch wrapper for device
+memory and streams (``api``), and the autograd adjoint (``autograd``).
+Importing the package fails if the library has not been built.
+"""
+from . import _lib  # noqa: F401  (raises ImportError when libhgrape.so is missing)
+from .api import Context, EvalResult, Problem, evaluate, plan, step_norms  # noqa: F401
+
+__all__ = ["Context", "Problem", "EvalResult", "evaluate", "plan", "step_norms"]

@@ -1,0 +1,529 @@
+// C ABI of libhgrape: validation, operator conversion (CSR -> DIA on the
+// device), evaluation orchestration (norms -> host planner -> sweeps).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "hg_internal.h"
+
+namespace hg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+hg_status fail(hg_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+hg_status hip_fail(hipError_t e, const char* what) {
+  return fail(HG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HG_HIP(call)                                  \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+struct Entry {
+  int64_t col;
+  double re, im;
+};
+
+// Validated, duplicate-summed rows of one CSR operator (explicit zeros dropped).
+hg_status read_csr(const hg_csr* m, int64_t dim, const char* name,
+                   std::vector<std::vector<Entry>>* rows) {
+  if (!m || m->n != dim || !m->indptr) return fail(HG_ERR_INVALID_ARG, std::string(name) + ": shape or indptr");
+  if (m->indptr[0] != 0) return fail(HG_ERR_INVALID_ARG, std::string(name) + ": indptr[0] != 0");
+  for (int64_t i = 0; i < dim; ++i)
+    if (m->indptr[i + 1] < m->indptr[i])
+      return fail(HG_ERR_INVALID_ARG, std::string(name) + ": indptr not monotone");
+  const int64_t nnz = m->indptr[dim];
+  if (nnz > 0 && (!m->indices || !m->values))
+    return fail(HG_ERR_INVALID_ARG, std::string(name) + ": missing indices/values");
+  rows->assign(dim, {});
+  for (int64_t i = 0; i < dim; ++i) {
+    std::map<int64_t, std::pair<double, double>> acc;
+    for (int64_t p = m->indptr[i]; p < m->indptr[i + 1]; ++p) {
+      const int64_t j = m->indices[p];
+      if (j < 0 || j >= dim) return fail(HG_ERR_INVALID_ARG, std::string(name) + ": column out of range");
+      const double re = m->values[2 * p], im = m->values[2 * p + 1];
+      if (!std::isfinite(re) || !std::isfinite(im))
+        return fail(HG_ERR_NONFINITE, std::string(name) + ": non-finite value");
+      auto& a = acc[j];
+      a.first += re;
+      a.second += im;
+    }
+    for (auto& kv : acc)
+      if (kv.second.first != 0.0 || kv.second.second != 0.0)
+        (*rows)[i].push_back({kv.first, kv.second.first, kv.second.second});
+  }
+  return HG_OK;
+}
+
+hg_status check_hermitian(const std::vector<std::vector<Entry>>& rows, const char* name) {
+  double amax = 0.0;
+  for (auto& r : rows)
+    for (auto& e : r) amax = std::max(amax, std::hypot(e.re, e.im));
+  const double tol = 1e-12 * (amax > 0 ? amax : 1.0);
+  auto find = [&](int64_t i, int64_t j, double* re, double* im) {
+    const auto& r = rows[i];
+    auto it = std::lower_bound(r.begin(), r.end(), j,
+                               [](const Entry& e, int64_t c) { return e.col < c; });
+    if (it != r.end() && it->col == j) {
+      *re = it->re;
+      *im = it->im;
+    } else {
+      *re = 0.0;
+      *im = 0.0;
+    }
+  };
+  for (int64_t i = 0; i < (int64_t)rows.size(); ++i)
+    for (auto& e : rows[i]) {
+      double tr, ti;
+      find(e.col, i, &tr, &ti);
+      if (std::fabs(e.re - tr) > tol || std::fabs(e.im + ti) > tol)
+        return fail(HG_ERR_NOT_HERMITIAN, std::string(name) + " is not Hermitian at (" +
+                                              std::to_string(i) + "," + std::to_string(e.col) + ")");
+    }
+  return HG_OK;
+}
+
+}  // namespace
+}  // namespace hg
+
+using namespace hg;
+
+extern "C" {
+
+const char* hg_status_string(hg_status s) {
+  switch (s) {
+    case HG_OK: return "ok";
+    case HG_ERR_INVALID_ARG: return "invalid argument";
+    case HG_ERR_NOT_HERMITIAN: return "operator not Hermitian";
+    case HG_ERR_NONFINITE: return "non-finite input";
+    case HG_ERR_TOLERANCE_UNREACHABLE: return "tolerance unreachable";
+    case HG_ERR_OUT_OF_MEMORY: return "out of memory";
+    case HG_ERR_DEVICE: return "device error";
+    case HG_ERR_BUSY: return "busy";
+    case HG_ERR_CANCELLED: return "cancelled";
+    case HG_ERR_UNSUPPORTED: return "unsupported shape";
+  }
+  return "unknown status";
+}
+
+const char* hg_last_error(void) { return g_last_error.c_str(); }
+
+int32_t hg_version(void) { return 100; }
+
+hg_status hg_create(int device_ordinal, hg_ctx** out) {
+  if (!out) return fail(HG_ERR_INVALID_ARG, "out is NULL");
+  int n = 0;
+  HG_HIP(hipGetDeviceCount(&n));
+  if (device_ordinal < 0 || device_ordinal >= n)
+    return fail(HG_ERR_INVALID_ARG, "device ordinal out of range");
+  HG_HIP(hipSetDevice(device_ordinal));
+  auto c = std::make_unique<hg_ctx>();
+  c->device = device_ordinal;
+  int v = 0;
+  HG_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device_ordinal));
+  c->num_cu = v;
+  HG_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device_ordinal));
+  c->lds_per_block = (size_t)v;
+  *out = c.release();
+  return HG_OK;
+}
+
+hg_status hg_destroy(hg_ctx* ctx) {
+  delete ctx;
+  return HG_OK;
+}
+
+hg_status hg_problem_create(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, const hg_csr* H0,
+                            const hg_csr* Hk, const double* omega_diag, hg_problem** out) {
+  if (!ctx || !out || !H0) return fail(HG_ERR_INVALID_ARG, "NULL argument");
+  if (dim < 1 || dim > (int64_t)kMaxThreads * kMaxRows)
+    return fail(dim < 1 ? HG_ERR_INVALID_ARG : HG_ERR_UNSUPPORTED,
+                "dim must be in [1, " + std::to_string(kMaxThreads * kMaxRows) + "]");
+  if (n_ctrl < 0 || n_ctrl > kMaxCtrl)
+    return fail(n_ctrl < 0 ? HG_ERR_INVALID_ARG : HG_ERR_UNSUPPORTED, "n_ctrl out of range");
+  if (n_ctrl > 0 && !Hk) return fail(HG_ERR_INVALID_ARG, "Hk is NULL");
+  HG_HIP(hipSetDevice(ctx->device));
+
+  const int K = n_ctrl;
+  std::vector<std::vector<std::vector<Entry>>> ops(K + 1);
+  hg_status st = read_csr(H0, dim, "H0", &ops[0]);
+  if (st != HG_OK) return st;
+  if ((st = check_hermitian(ops[0], "H0")) != HG_OK) return st;
+  for (int k = 0; k < K; ++k) {
+    const std::string nm = "H" + std::to_string(k + 1);
+    if ((st = read_csr(&Hk[k], dim, nm.c_str(), &ops[k + 1])) != HG_OK) return st;
+    if ((st = check_hermitian(ops[k + 1], nm.c_str())) != HG_OK) return st;
+  }
+  if (omega_diag)
+    for (int64_t i = 0; i < dim; ++i)
+      if (!std::isfinite(omega_diag[i])) return fail(HG_ERR_NONFINITE, "omega: non-finite value");
+
+  // union diagonals, per-control diagonals, sigma' and structural counts
+  std::set<int64_t> uoff;
+  std::vector<std::set<int64_t>> koff(K);
+  int64_t sigma = 0, nnz = 0;
+  std::vector<int64_t> nnz_ctrl(K, 0);
+  for (int64_t i = 0; i < dim; ++i) {
+    std::set<int64_t> cols;
+    for (int o = 0; o <= K; ++o)
+      for (auto& e : ops[o][i]) {
+        cols.insert(e.col);
+        uoff.insert(e.col - i);
+        if (o > 0) {
+          koff[o - 1].insert(e.col - i);
+          nnz_ctrl[o - 1]++;
+        }
+      }
+    sigma = std::max<int64_t>(sigma, (int64_t)cols.size());
+    nnz += (int64_t)cols.size();
+  }
+  if (uoff.empty()) uoff.insert(0);
+  if ((int)uoff.size() > kMaxDiag)
+    return fail(HG_ERR_UNSUPPORTED, "union pattern has " + std::to_string(uoff.size()) +
+                                        " diagonals; the DIA kernels support at most 13");
+  for (int k = 0; k < K; ++k)
+    if ((int)koff[k].size() > kMaxDiagCtrl)
+      return fail(HG_ERR_UNSUPPORTED, "control " + std::to_string(k + 1) + " has " +
+                                          std::to_string(koff[k].size()) + " diagonals (max 4)");
+
+  auto p = std::make_unique<hg_problem>();
+  p->ctx = ctx;
+  p->dim = dim;
+  p->n_ctrl = K;
+  p->sigma = (int32_t)std::max<int64_t>(sigma, 1);
+  p->nnz = nnz;
+  p->nnz_ctrl = nnz_ctrl;
+  DevOps& d = p->ops;
+  d.W = (int)uoff.size();
+  std::map<int64_t, int> slot;
+  int e = 0;
+  for (int64_t o : uoff) {
+    d.off[e] = (int)o;
+    slot[o] = e++;
+    d.halo = std::max<int>(d.halo, (int)std::llabs(o));
+  }
+  for (int k = 0; k < K; ++k) {
+    d.WK[k] = (int)koff[k].size();
+    int q = 0;
+    for (int64_t o : koff[k]) d.offk[k][q++] = (int)o;
+  }
+  std::vector<double2> hv((size_t)(K + 1) * d.W * dim, double2{0.0, 0.0});
+  std::vector<double2> hk((size_t)std::max(K, 1) * kMaxDiagCtrl * dim, double2{0.0, 0.0});
+  for (int o = 0; o <= K; ++o)
+    for (int64_t i = 0; i < dim; ++i)
+      for (auto& en : ops[o][i]) {
+        const int64_t off = en.col - i;
+        hv[((size_t)o * d.W + slot[off]) * dim + i] = double2{en.re, en.im};
+        if (o > 0) {
+          int q = 0;
+          while (d.offk[o - 1][q] != off) ++q;
+          hk[((size_t)(o - 1) * kMaxDiagCtrl + q) * dim + i] = double2{en.re, en.im};
+        }
+      }
+  HG_HIP(hipMalloc(&d.vals, hv.size() * sizeof(double2)));
+  HG_HIP(hipMemcpy(d.vals, hv.data(), hv.size() * sizeof(double2), hipMemcpyHostToDevice));
+  HG_HIP(hipMalloc(&d.valk, hk.size() * sizeof(double2)));
+  HG_HIP(hipMemcpy(d.valk, hk.data(), hk.size() * sizeof(double2), hipMemcpyHostToDevice));
+  if (omega_diag) {
+    HG_HIP(hipMalloc(&d.omega, dim * sizeof(double)));
+    HG_HIP(hipMemcpy(d.omega, omega_diag, dim * sizeof(double), hipMemcpyHostToDevice));
+  }
+  *out = p.release();
+  return HG_OK;
+}
+
+hg_status hg_problem_destroy(hg_problem* p) {
+  if (!p) return HG_OK;
+  hipSetDevice(p->ctx->device);
+  if (p->ops.vals) hipFree(p->ops.vals);
+  if (p->ops.valk) hipFree(p->ops.valk);
+  if (p->ops.omega) hipFree(p->ops.omega);
+  delete p;
+  return HG_OK;
+}
+
+hg_status hg_problem_info(const hg_problem* p, int64_t* dim, int32_t* n_ctrl, int32_t* ell_width,
+                          int32_t* sigma, int64_t* nnz) {
+  if (!p) return fail(HG_ERR_INVALID_ARG, "problem is NULL");
+  if (dim) *dim = p->dim;
+  if (n_ctrl) *n_ctrl = p->n_ctrl;
+  if (ell_width) *ell_width = p->ops.W;
+  if (sigma) *sigma = p->sigma;
+  if (nnz) *nnz = p->nnz;
+  return HG_OK;
+}
+
+double hg_error_bound(double theta, int32_t m, int32_t s, int32_t sigma, double u) {
+  if (m < 1 || s < 1 || sigma < 1 || !(theta >= 0.0)) return std::nan("");
+  return error_bound(theta, m, s, sigma, u);
+}
+
+hg_status hg_plan(const double* theta, int64_t n, int32_t sigma, double tau, double u,
+                  int32_t* m_out, int32_t* s_out) {
+  if (n < 0 || (n > 0 && (!theta || !m_out || !s_out)) || sigma < 1 || !(tau > 0.0) ||
+      !(u > 0.0 && u < 0.25))
+    return fail(HG_ERR_INVALID_ARG, "hg_plan: bad argument");
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(theta[i])) return fail(HG_ERR_NONFINITE, "norm " + std::to_string(i) + " is not finite");
+    if (theta[i] < 0.0) return fail(HG_ERR_INVALID_ARG, "negative norm");
+  }
+  int64_t bad = -1;
+  const int rc = plan_steps(theta, n, sigma, tau, u, m_out, s_out, &bad);
+  if (rc == 2)
+    return fail(HG_ERR_UNSUPPORTED, "step " + std::to_string(bad) + " (norm " +
+                                        std::to_string(theta[bad]) + ") would need s > " +
+                                        std::to_string(kSMax) + "; shorten dt");
+  if (rc != 0) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf),
+                  "no (m<=%d, s) meets E_A <= %g at step %lld (norm %.6g); the rounding floor of "
+                  "the bound exceeds the tolerance",
+                  kMMax, tau, (long long)bad, theta[bad]);
+    return fail(HG_ERR_TOLERANCE_UNREACHABLE, buf);
+  }
+  return HG_OK;
+}
+
+hg_status hg_step_norms(hg_problem* p, const double* u, int32_t n_batch, int32_t n_steps,
+                        double dt, double* theta_out, void* stream) {
+  if (!p || !u || !theta_out || n_batch < 1 || n_steps < 1)
+    return fail(HG_ERR_INVALID_ARG, "hg_step_norms: bad argument");
+  if (!std::isfinite(dt) || !(dt > 0.0)) return fail(HG_ERR_INVALID_ARG, "dt must be finite and > 0");
+  HG_HIP(hipSetDevice(p->ctx->device));
+  HG_HIP(launch_step_norms(p->ops, (int)p->dim, p->n_ctrl, u, n_batch, n_steps, dt, theta_out,
+                           (hipStream_t)stream));
+  return HG_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Workspace {
+  size_t theta, pnorm, sched, psiN, cold, ovl, pen, gradp, drift, res, total;
+};
+
+static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128) {
+  const size_t cs = c128 ? 16 : 8;
+  const size_t d = (size_t)p->dim, K = (size_t)p->n_ctrl;
+  Workspace w{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  w.theta = take((size_t)B * N * 8);
+  w.pnorm = take((size_t)B * S * 8);
+  w.sched = take((size_t)2 * B * N * 4);
+  w.psiN = take((size_t)B * S * d * cs);
+  w.cold = take((size_t)B * S * 3 * d * cs);
+  w.ovl = take((size_t)B * S * 16);
+  w.pen = take((size_t)B * S * 8);
+  w.gradp = take((size_t)B * S * std::max<size_t>(K, 1) * N * 8);
+  w.drift = take((size_t)B * S * 8);
+  w.res = take((size_t)B * 8 * 8);
+  w.total = o;
+  return w;
+}
+
+static hg_status check_desc(const hg_problem* p, const hg_eval_desc* d) {
+  if (!p || !d) return fail(HG_ERR_INVALID_ARG, "NULL problem or desc");
+  if (d->n_steps < 1) return fail(HG_ERR_INVALID_ARG, "n_steps must be >= 1");
+  if (d->n_batch < 1) return fail(HG_ERR_INVALID_ARG, "n_batch must be >= 1");
+  if (d->n_states < 1) return fail(HG_ERR_INVALID_ARG, "n_states must be >= 1");
+  if (!std::isfinite(d->dt) || !(d->dt > 0.0)) return fail(HG_ERR_INVALID_ARG, "dt must be finite and > 0");
+  if (!std::isfinite(d->w_fid) || !std::isfinite(d->w_pen)) return fail(HG_ERR_NONFINITE, "weights");
+  if (!(d->tau > 0.0) || !std::isfinite(d->tau)) return fail(HG_ERR_INVALID_ARG, "tau must be > 0");
+  if (d->dtype != HG_C64 && d->dtype != HG_C128) return fail(HG_ERR_INVALID_ARG, "dtype");
+  if (d->mode != HG_MODE_RECONSTRUCT) {
+    if (d->mode != HG_MODE_CHECKPOINT) return fail(HG_ERR_INVALID_ARG, "mode");
+    return fail(HG_ERR_UNSUPPORTED, "checkpoint mode is not built yet");
+  }
+  if (d->renorm_every < 0) return fail(HG_ERR_INVALID_ARG, "renorm_every must be >= 0");
+  if ((p->n_ctrl > 0 && !d->u) || !d->psi0 || !d->targets)
+    return fail(HG_ERR_INVALID_ARG, "NULL device array");
+  return HG_OK;
+}
+
+hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* d, size_t* bytes) {
+  hg_status st = check_desc(p, d);
+  if (st != HG_OK) return st;
+  if (!bytes) return fail(HG_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = layout(p, d->n_batch, d->n_steps, d->n_states, d->dtype == HG_C128).total;
+  return HG_OK;
+}
+
+hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, double* grad,
+                  void* stream) {
+  hg_status st = check_desc(p, d);
+  if (st != HG_OK) return st;
+  if (!results) return fail(HG_ERR_INVALID_ARG, "results is NULL");
+  const int B = d->n_batch, N = d->n_steps, S = d->n_states, K = p->n_ctrl;
+  const bool c128 = d->dtype == HG_C128;
+  hipStream_t hs = (hipStream_t)stream;
+  HG_HIP(hipSetDevice(p->ctx->device));
+
+  SweepShape sh{};
+  std::string why;
+  if (!sweep_supported(p->ops, (int)p->dim, K, c128, p->ctx->lds_per_block, &sh, &why))
+    return fail(HG_ERR_UNSUPPORTED, why);
+  sh.n_steps = N;
+  sh.n_states = S;
+  sh.n_batch = B;
+
+  const Workspace w = layout(p, B, N, S, c128);
+  char* ws = nullptr;
+  if (hipMallocAsync((void**)&ws, w.total, hs) != hipSuccess)
+    return fail(HG_ERR_OUT_OF_MEMORY, "workspace of " + std::to_string(w.total) + " bytes");
+  struct Free {
+    char* p;
+    hipStream_t s;
+    ~Free() {
+      if (p) hipFreeAsync(p, s);
+    }
+  } guard{ws, hs};
+
+  // host staging (pinned): norms, state norms, schedule, result scalars
+  const size_t hbytes = (size_t)B * N * 8 + (size_t)B * S * 8 + (size_t)2 * B * N * 4 +
+                        (size_t)B * 8 * 8 + (size_t)B * S * 8;
+  char* hbuf = nullptr;
+  HG_HIP(hipHostMalloc((void**)&hbuf, hbytes, hipHostMallocDefault));
+  struct HFree {
+    char* p;
+    ~HFree() {
+      if (p) hipHostFree(p);
+    }
+  } hguard{hbuf};
+  double* h_theta = (double*)hbuf;
+  double* h_pnorm = h_theta + (size_t)B * N;
+  int32_t* h_sched = (int32_t*)(h_pnorm + (size_t)B * S);
+  double* h_res = (double*)(h_sched + (size_t)2 * B * N);
+  double* h_drift = h_res + (size_t)B * 8;
+
+  double* d_theta = (double*)(ws + w.theta);
+  double* d_pnorm = (double*)(ws + w.pnorm);
+  int32_t* d_sched = (int32_t*)(ws + w.sched);
+  static const double kZeroU = 0.0;
+  const double* u_dev = d->u;
+  if (K == 0) u_dev = d_theta;  // never read (no controls); any valid pointer
+
+  // 1-norms of every step (App. C) and state norms, then the host planner
+  HG_HIP(launch_step_norms(p->ops, (int)p->dim, K, u_dev, B, N, d->dt, d_theta, hs));
+  HG_HIP(launch_state_norms(d->psi0, (int)p->dim, S, B, d_pnorm, hs));
+  HG_HIP(hipMemcpyAsync(h_theta, d_theta, (size_t)B * N * 8, hipMemcpyDeviceToHost, hs));
+  HG_HIP(hipMemcpyAsync(h_pnorm, d_pnorm, (size_t)B * S * 8, hipMemcpyDeviceToHost, hs));
+  HG_HIP(hipStreamSynchronize(hs));
+  (void)kZeroU;
+  for (int64_t i = 0; i < (int64_t)B * S; ++i)
+    if (!std::isfinite(h_pnorm[i]) || std::fabs(h_pnorm[i] - 1.0) > 1e-8)
+      return fail(std::isfinite(h_pnorm[i]) ? HG_ERR_INVALID_ARG : HG_ERR_NONFINITE,
+                  "initial state " + std::to_string(i) + " has norm " + std::to_string(h_pnorm[i]) +
+                      " (must be 1 to 1e-8)");
+  double max_theta = 0.0, max_bound = 0.0;
+  for (int64_t i = 0; i < (int64_t)B * N; ++i) {
+    if (!std::isfinite(h_theta[i]))
+      return fail(HG_ERR_NONFINITE, "amplitudes of step " + std::to_string(i % N) + " are not finite");
+    max_theta = std::max(max_theta, h_theta[i]);
+  }
+  int32_t* h_m = h_sched;
+  int32_t* h_s = h_sched + (size_t)B * N;
+  if (d->schedule) {
+    for (int64_t i = 0; i < (int64_t)B * N; ++i) {
+      h_m[i] = d->schedule[i];
+      h_s[i] = d->schedule[(size_t)B * N + i];
+      if (h_m[i] < 1 || h_m[i] > kMMax || h_s[i] < 1 || h_s[i] > kSMax)
+        return fail(HG_ERR_INVALID_ARG, "frozen schedule entry " + std::to_string(i) + " out of range");
+    }
+  } else {
+    // FP64 arithmetic bound (u = 2^-53) for both precisions: the schedule is
+    // chosen by the paper's rule for double arithmetic; complex64 then differs
+    // from complex128 only in the arithmetic of the products.
+    st = hg_plan(h_theta, (int64_t)B * N, p->sigma, d->tau, std::ldexp(1.0, -53), h_m, h_s);
+    if (st != HG_OK) return st;
+    for (int64_t i = 0; i < (int64_t)B * N; ++i)
+      max_bound = std::max(max_bound, error_bound(h_theta[i], h_m[i], h_s[i], p->sigma,
+                                                  std::ldexp(1.0, -53)));
+  }
+  HG_HIP(hipMemcpyAsync(d_sched, h_sched, (size_t)2 * B * N * 4, hipMemcpyHostToDevice, hs));
+
+  SweepBuffers bf{};
+  bf.u = u_dev;
+  bf.m_sched = d_sched;
+  bf.s_sched = d_sched + (size_t)B * N;
+  bf.psi0 = d->psi0;
+  bf.targets = d->targets;
+  bf.psiN = ws + w.psiN;
+  bf.cold = ws + w.cold;
+  bf.ovl = (double*)(ws + w.ovl);
+  bf.pen = (double*)(ws + w.pen);
+  bf.gradp = (double*)(ws + w.gradp);
+  bf.drift = (double*)(ws + w.drift);
+  bf.res = (double*)(ws + w.res);
+  bf.grad = grad;
+  bf.ev[0] = bf.ev[1] = bf.ev[2] = nullptr;
+  struct Events {
+    hipEvent_t* e;
+    ~Events() {
+      for (int i = 0; i < 3; ++i)
+        if (e[i]) hipEventDestroy(e[i]);
+    }
+  } evguard{bf.ev};
+  if (d->flags & HG_FLAG_TIMING)
+    for (int i = 0; i < 3; ++i) HG_HIP(hipEventCreate(&bf.ev[i]));
+  SweepParams sp{d->dt, d->w_fid, d->w_pen, d->renorm_every};
+  HG_HIP(launch_sweep(p->ops, sh, bf, sp, hs));
+  HG_HIP(hipMemcpyAsync(h_res, bf.res, (size_t)B * 8 * 8, hipMemcpyDeviceToHost, hs));
+  HG_HIP(hipMemcpyAsync(h_drift, bf.drift, (size_t)B * S * 8, hipMemcpyDeviceToHost, hs));
+  HG_HIP(hipStreamSynchronize(hs));
+  float ms_f = 0.f, ms_b = 0.f;
+  if (d->flags & HG_FLAG_TIMING) {
+    HG_HIP(hipEventElapsedTime(&ms_f, bf.ev[0], bf.ev[1]));
+    HG_HIP(hipEventElapsedTime(&ms_b, bf.ev[1], bf.ev[2]));
+  }
+
+  for (int b = 0; b < B; ++b) {
+    hg_result& r = results[b];
+    r.cost = h_res[b * 8 + 0];
+    r.infidelity = h_res[b * 8 + 1];
+    r.penalty = h_res[b * 8 + 2];
+    r.overlap_re = h_res[b * 8 + 3];
+    r.overlap_im = h_res[b * 8 + 4];
+    int64_t mu = 0;
+    double mt = 0.0, mb = 0.0, dr = 0.0;
+    for (int n = 0; n < N; ++n) {
+      const size_t i = (size_t)b * N + n;
+      mu += (int64_t)h_m[i] * h_s[i];
+      mt = std::max(mt, h_theta[i]);
+      if (!d->schedule)
+        mb = std::max(mb, error_bound(h_theta[i], h_m[i], h_s[i], p->sigma, std::ldexp(1.0, -53)));
+    }
+    for (int h = 0; h < S; ++h) dr = std::max(dr, h_drift[(size_t)b * S + h]);
+    r.sum_mu = mu;
+    r.max_theta = mt;
+    r.max_bound = mb;
+    r.drift = dr;
+    r.ms_forward = ms_f;
+    r.ms_backward = ms_b;
+  }
+  (void)max_bound;
+  return HG_OK;
+}
+
+}  // extern "C"

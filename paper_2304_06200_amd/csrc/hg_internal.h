@@ -1,0 +1,103 @@
+// Internal declarations shared by the host sources of libhgrape.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hgrape.h"
+
+namespace hg {
+
+constexpr int kMaxDiag = 16;      // diagonals of the union pattern (DIA width)
+constexpr int kMaxDiagCtrl = 4;   // diagonals of one control operator
+constexpr int kMaxCtrl = 16;      // control channels
+constexpr int kMaxThreads = 512;  // threads per workgroup (2 waves per SIMD)
+constexpr int kMaxRows = 8;       // rows per thread
+constexpr int kMMax = 60;         // largest Taylor degree the planner may choose
+constexpr int kSMax = 4096;       // largest scaling factor one step may use
+
+void set_error(const std::string& msg);
+
+// Operators on the device in diagonal (DIA) storage.  Row i of diagonal e
+// holds the entry (i, i + off[e]), zero where that column is outside the matrix.
+struct DevOps {
+  int W = 0;                       // number of union diagonals
+  int off[kMaxDiag] = {0};
+  int WK[kMaxCtrl] = {0};          // diagonals per control
+  int offk[kMaxCtrl][kMaxDiagCtrl] = {{0}};
+  int halo = 0;                    // max |off|: LDS halo on each side of a vector
+  double2* vals = nullptr;         // [(K+1)][W][dim]: H0 then H_1..H_K on the union pattern
+  double2* valk = nullptr;         // [K][kMaxDiagCtrl][dim]: each H_k on its own diagonals
+  double* omega = nullptr;         // [dim] or nullptr
+};
+
+}  // namespace hg
+
+struct hg_ctx {
+  int device = 0;
+  int num_cu = 0;
+  size_t lds_per_block = 0;
+};
+
+struct hg_problem {
+  hg_ctx* ctx = nullptr;
+  int64_t dim = 0;
+  int32_t n_ctrl = 0;
+  int32_t sigma = 0;               // max non-zeros in a row of the union pattern
+  int64_t nnz = 0;                 // stored union non-zeros (structural)
+  std::vector<int64_t> nnz_ctrl;   // structural non-zeros of each H_k
+  hg::DevOps ops;
+};
+
+namespace hg {
+
+// Planner (plan.cpp): FP64, no contraction, the same operation order as the
+// bound of App. C.
+double error_bound(double theta, int m, int s, int sigma, double u);
+// Returns 0 on success, 1 if unreachable, 2 if a solution would need s > 4096
+// (then *fail_index is the failing index).
+int plan_steps(const double* theta, int64_t n, int sigma, double tau, double u,
+               int32_t* m_out, int32_t* s_out, int64_t* fail_index);
+
+// Kernel launchers (kernels.hip).
+struct SweepShape {
+  int dim, n_ctrl, n_steps, n_states, n_batch;
+  int rows_per_thread, threads, groups;  // groups = controls per backward pass
+  size_t lds_fwd, lds_bwd;
+  bool c128;
+};
+hipError_t launch_step_norms(const DevOps& ops, int dim, int K, const double* u, int nb,
+                             int N, double dt, double* theta, hipStream_t st);
+hipError_t launch_state_norms(const double* psi, int dim, int S, int nb, double* out,
+                              hipStream_t st);
+
+struct SweepBuffers {
+  const double* u;
+  const int32_t* m_sched;          // [B][N]
+  const int32_t* s_sched;          // [B][N]
+  const double* psi0;              // [B][S][dim] complex128
+  const double* targets;           // [B][S][dim] complex128
+  void* psiN;                      // [B][S][dim] working precision
+  void* cold;                      // [B][S][3][dim] working precision
+  double* ovl;                     // [B][S][2]
+  double* pen;                     // [B][S]
+  double* gradp;                   // [B][S][K][N]
+  double* drift;                   // [B][S]
+  double* res;                     // [B][8]
+  double* grad;                    // [B][K][N] or nullptr
+  hipEvent_t ev[3];                // optional: before forward, between, after backward
+};
+struct SweepParams {
+  double dt, w_fid, w_pen;
+  int renorm_every;
+};
+bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_limit,
+                     SweepShape* shape, std::string* why);
+hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuffers& b,
+                        const SweepParams& p, hipStream_t st);
+
+}  // namespace hg

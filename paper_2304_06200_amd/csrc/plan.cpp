@@ -1,0 +1,125 @@
+// Host planner: the error bound E_A(m, s) of App. C and the (m, s) selection
+// rule of Sec. III.B, in FP64.  Built with -ffp-contract=off so every product
+// and sum is rounded exactly as written.
+//
+//   R_m(x)  = sum_{q>m} x^q/q!                          (App. C.1)
+//   trunc   = sR (1 - (sR)^s) / (1 - sR), R = R_m(theta/s)   (App. C.1, eq. truncation)
+//   u'      = 2 sqrt(2) u / (1 - 2u),  gamma_n = n u'/(1 - n u')  (App. C.2)
+//   beta    = sum_{k=0..m} gamma_{k(sigma+2)+m+2} (theta/s)^k / k!   (App. C.2, eq. B23)
+//   alpha   = 1 + R                                      (App. C.3)
+//   E_A     = trunc + (alpha+beta)^s - alpha^s           (App. C, eq. overallupperbound)
+//
+// Readings: sR >= 1 is infeasible; gamma_n is infinite once n u' >= 1; the
+// tail is summed directly until a term drops below 1e-18 of the sum; the
+// rounding part is evaluated as alpha^s expm1(s log1p(beta/alpha)); s runs
+// 1, 2, ... up to floor(tau / gamma_3), m runs 1..60, first hit wins.
+#include <cmath>
+#include <cstdint>
+#include <limits>
+
+namespace hg {
+
+namespace {
+
+double u_prime(double u) { return 2.0 * std::sqrt(2.0) * u / (1.0 - 2.0 * u); }
+
+double gamma_n(int64_t n, double up) {
+  double nu = (double)n * up;
+  if (nu >= 1.0) return std::numeric_limits<double>::infinity();
+  return nu / (1.0 - nu);
+}
+
+double taylor_tail(double x, int m) {
+  if (x == 0.0) return 0.0;
+  double t = 1.0;
+  for (int q = 1; q <= m + 1; ++q) t = t * x / (double)q;
+  double total = t;
+  int q = m + 1;
+  for (;;) {
+    q += 1;
+    t = t * x / (double)q;
+    total += t;
+    if (!(t >= 1e-18 * total) || std::isinf(total)) break;
+  }
+  return total;
+}
+
+// beta of App. C.2 (eq. B23) at scaled norm x.
+double beta_of(double x, int m, int sigma, double up) {
+  double beta = 0.0;
+  double t = 1.0;
+  for (int k = 0; k <= m; ++k) {
+    if (k > 0) t = t * x / (double)k;
+    beta += gamma_n((int64_t)k * (sigma + 2) + m + 2, up) * t;
+  }
+  return beta;
+}
+
+}  // namespace
+
+double error_bound(double theta, int m, int s, int sigma, double u) {
+  const double x = theta / (double)s;
+  const double R = taylor_tail(x, m);
+  const double sR = (double)s * R;
+  if (!(sR < 1.0)) return std::numeric_limits<double>::infinity();
+  const double trunc = sR * (1.0 - std::pow(sR, (double)s)) / (1.0 - sR);
+  const double up = u_prime(u);
+  const double alpha = 1.0 + R;
+  const double beta = beta_of(x, m, sigma, up);
+  if (std::isinf(beta)) return std::numeric_limits<double>::infinity();
+  const double rnd = std::pow(alpha, (double)s) * std::expm1((double)s * std::log1p(beta / alpha));
+  return trunc + rnd;
+}
+
+// Smallest s, then smallest m (Sec. III.B).  The inner scan over m may stop
+// early once s*beta(m) > 2 tau: the rounding part (alpha+beta)^s - alpha^s is at
+// least s*beta and beta grows with m, so no larger m can satisfy the bound
+// (the factor 2 keeps the shortcut clear of rounding in the comparison).
+// Returns 0 on success, 1 if no (m, s) exists, 2 if one might exist only
+// beyond s = kSCap (a single step would then cost more than 60*kSCap products).
+static constexpr int64_t kSCap = 4096;
+static int select_one(double theta, int sigma, double tau, double u, int32_t* m_out,
+                      int32_t* s_out) {
+  const double up = u_prime(u);
+  const double g3 = gamma_n(3, up);
+  int64_t s_lim = (int64_t)(tau / g3);
+  if (s_lim < 1) s_lim = 1;
+  const bool capped = s_lim > kSCap;
+  if (capped) s_lim = kSCap;
+  for (int64_t s = 1; s <= s_lim; ++s) {
+    const double x = theta / (double)s;
+    for (int m = 1; m <= 60; ++m) {
+      if (error_bound(theta, m, (int)s, sigma, u) <= tau) {
+        *m_out = m;
+        *s_out = (int32_t)s;
+        return 0;
+      }
+      if ((double)s * beta_of(x, m, sigma, up) > 2.0 * tau) break;
+    }
+  }
+  return capped ? 2 : 1;
+}
+
+int plan_steps(const double* theta, int64_t n, int sigma, double tau, double u, int32_t* m_out,
+               int32_t* s_out, int64_t* fail_index) {
+  double last_theta = std::numeric_limits<double>::quiet_NaN();
+  int32_t last_m = 0, last_s = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (theta[i] == last_theta) {  // identical norm: identical choice
+      m_out[i] = last_m;
+      s_out[i] = last_s;
+      continue;
+    }
+    const int rc = select_one(theta[i], sigma, tau, u, &m_out[i], &s_out[i]);
+    if (rc != 0) {
+      *fail_index = i;
+      return rc;
+    }
+    last_theta = theta[i];
+    last_m = m_out[i];
+    last_s = s_out[i];
+  }
+  return 0;
+}
+
+}  // namespace hg

@@ -1,0 +1,528 @@
+// Device code of the HG-GRAPE sweep for gfx950 (included by sweep_w*.hip).
+//
+// Work decomposition.  One workgroup owns one state column h of one
+// evaluation b for the whole time axis (the chain psi_0 -> psi_N is strictly
+// sequential, Sec. II).  Each thread owns RPT rows (row = tid + r*NT, so a
+// wavefront touches consecutive rows).  For step n the thread assembles its
+// rows of B_n = -i dt H_n / s_n on the W union diagonals into registers once
+// and reuses them for all m_n s_n Taylor terms.
+//
+// Term vectors live in LDS as a *state block*: row i of the block holds the
+// V vectors that are propagated together (1 in the forward sweep, psi and
+// Lambda in the reconstruction, Y and X_1..X_G in the auxiliary action), so
+// one wide ds_read per (row, diagonal) fetches all of them and one address
+// register per (row, diagonal) serves every vector.  The block is double
+// buffered (one barrier per Taylor term) and framed by `halo` zero rows on
+// both sides, so the shifted reads at i + off_e need no clamping or bounds
+// tests.  Accumulators stay in registers.  Norms, overlaps and gradient
+// partials are accumulated in FP64 and reduced in a fixed order
+// (deterministic, bitwise reproducible).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hg_internal.h"
+
+namespace hg {
+
+constexpr int kRedBytes = 1024;  // FP64 reduction scratch at the start of LDS
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cx {
+  R re, im;
+};
+
+struct SweepArgs {
+  int d, K, N, S, W, halo, G, renorm_every;
+  int off[kMaxDiag];
+  int WK[kMaxCtrl];
+  int offk[kMaxCtrl][kMaxDiagCtrl];
+  const double2* vals;   // [(K+1)][W][d]
+  const double2* valk;   // [K][kMaxDiagCtrl][d]
+  const double* omega;   // [d] or nullptr
+  const double* u;       // [B][K][N]
+  const int* msch;       // [B][N]
+  const int* ssch;       // [B][N]
+  const double2* psi0;   // [B][S][d]
+  const double2* tgt;    // [B][S][d]
+  void* psiN;            // [B][S][d] (working precision)
+  void* cold;            // [B][S][3][d] (working precision)
+  double* ovl;           // [B][S][2]
+  double* pen;           // [B][S]
+  double* gradp;         // [B][S][K][N]
+  double* drift;         // [B][S]
+  double* res;           // [B][8]
+  double dt, w_fid, w_pen;
+};
+
+// Rows of the LDS state block: [halo zero rows][d rows][halo zero rows].
+__host__ __device__ inline int block_rows(int d, int halo) { return d + 2 * halo; }
+
+template <typename R>
+__device__ __forceinline__ void cmac(cx<R>& acc, const cx<R>& a, const cx<R>& b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+
+// Hide a value from loop-invariant code motion: address arithmetic built on
+// it is redone where it is used instead of being hoisted out of the time loop
+// (which would pin one 64-bit address per operator entry in registers).
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Deterministic FP64 block sum of NV values; every thread receives the totals.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[i * 16 + w] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
+    for (int k = 0; k < nw; ++k) s += red[i * 16 + k];
+    v[i] = s;
+  }
+}
+
+// Rows of B_n = -i (dt/s) (H_0 + sum_k u_k H_k) on the union diagonals,
+// assembled in FP64 and rounded once to the working precision.
+template <typename R, int RPT, int W>
+__device__ __forceinline__ void assemble_B(const SweepArgs& a, const double* ub, int n,
+                                           const int (&row)[RPT], const bool (&ok)[RPT],
+                                           double cs, cx<R> (&bv)[RPT][W]) {
+  const int d = a.d;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = opaque(row[r]);
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      double hr = 0.0, hi = 0.0;
+      if (e < a.W && ok[r]) {
+        const double2 v0 = a.vals[(size_t)e * d + i];
+        hr = v0.x;
+        hi = v0.y;
+        for (int k = 0; k < a.K; ++k) {
+          const double c = ub[(size_t)k * a.N + n];
+          const double2 v = a.vals[((size_t)(k + 1) * a.W + e) * d + i];
+          hr = fma(c, v.x, hr);
+          hi = fma(c, v.y, hi);
+        }
+      }
+      bv[r][e].re = (R)(cs * hi);
+      bv[r][e].im = (R)(-cs * hr);
+    }
+  }
+}
+
+// E_k/s = -i (dt/s) H_k on the control's own diagonals (FP64 -> working precision).
+template <typename R, int RPT, int WK>
+__device__ __forceinline__ void load_E(const SweepArgs& a, int k, bool active,
+                                       const int (&row)[RPT], const bool (&ok)[RPT], double cs,
+                                       cx<R> (&ek)[RPT][WK]) {
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = opaque(row[r]);
+#pragma unroll
+    for (int q = 0; q < WK; ++q) {
+      double er = 0.0, ei = 0.0;
+      if (active && q < a.WK[k] && ok[r]) {
+        const double2 v = a.valk[((size_t)k * kMaxDiagCtrl + q) * a.d + i];
+        er = cs * v.y;
+        ei = -cs * v.x;
+      }
+      ek[r][q] = cx<R>{(R)er, (R)ei};
+    }
+  }
+}
+
+// 1/j for the Taylor recursion, read through the scalar cache (uniform index).
+__constant__ float kInvF[kMMax + 1] = {
+    0.f,         1.f,         1.f / 2,  1.f / 3,  1.f / 4,  1.f / 5,  1.f / 6,  1.f / 7,
+    1.f / 8,     1.f / 9,     1.f / 10, 1.f / 11, 1.f / 12, 1.f / 13, 1.f / 14, 1.f / 15,
+    1.f / 16,    1.f / 17,    1.f / 18, 1.f / 19, 1.f / 20, 1.f / 21, 1.f / 22, 1.f / 23,
+    1.f / 24,    1.f / 25,    1.f / 26, 1.f / 27, 1.f / 28, 1.f / 29, 1.f / 30, 1.f / 31,
+    1.f / 32,    1.f / 33,    1.f / 34, 1.f / 35, 1.f / 36, 1.f / 37, 1.f / 38, 1.f / 39,
+    1.f / 40,    1.f / 41,    1.f / 42, 1.f / 43, 1.f / 44, 1.f / 45, 1.f / 46, 1.f / 47,
+    1.f / 48,    1.f / 49,    1.f / 50, 1.f / 51, 1.f / 52, 1.f / 53, 1.f / 54, 1.f / 55,
+    1.f / 56,    1.f / 57,    1.f / 58, 1.f / 59, 1.f / 60};
+__constant__ double kInvD[kMMax + 1] = {
+    0.,        1.,        1. / 2,  1. / 3,  1. / 4,  1. / 5,  1. / 6,  1. / 7,  1. / 8,
+    1. / 9,    1. / 10,   1. / 11, 1. / 12, 1. / 13, 1. / 14, 1. / 15, 1. / 16, 1. / 17,
+    1. / 18,   1. / 19,   1. / 20, 1. / 21, 1. / 22, 1. / 23, 1. / 24, 1. / 25, 1. / 26,
+    1. / 27,   1. / 28,   1. / 29, 1. / 30, 1. / 31, 1. / 32, 1. / 33, 1. / 34, 1. / 35,
+    1. / 36,   1. / 37,   1. / 38, 1. / 39, 1. / 40, 1. / 41, 1. / 42, 1. / 43, 1. / 44,
+    1. / 45,   1. / 46,   1. / 47, 1. / 48, 1. / 49, 1. / 50, 1. / 51, 1. / 52, 1. / 53,
+    1. / 54,   1. / 55,   1. / 56, 1. / 57, 1. / 58, 1. / 59, 1. / 60};
+
+template <typename R>
+__device__ __forceinline__ R inv_int(int j);
+template <>
+__device__ __forceinline__ float inv_int<float>(int j) { return kInvF[j]; }
+template <>
+__device__ __forceinline__ double inv_int<double>(int j) { return kInvD[j]; }
+
+// One Taylor term for the V vectors of this thread's rows:
+//   t^v = sgn/j * (sum_e B[r][e] src^v[row + off_e]  (+ E_k/s src^Y[row + offk] for AUX tops))
+//   acc += t ; dst = t
+// The gathers are software-pipelined: a ring of PD+1 register slots keeps PD
+// LDS reads in flight ahead of the FMAs that consume them, and a scheduling
+// barrier after each item pins that order.  Items run row by row: first the W
+// union diagonals (a V-wide read each), then for AUX the (V-1)*WK derivative
+// operand reads (the Y entry only).
+template <typename R, int RPT, int W, int V, int WK, bool AUX>
+__device__ __forceinline__ void taylor_term(const cx<R>* src, cx<R>* dst, const SweepArgs& a,
+                                            int g0, const int (&row)[RPT], const bool (&ok)[RPT],
+                                            const cx<R> (&bv)[RPT][W],
+                                            const cx<R> (&ek)[V][RPT][WK], R inv,
+                                            cx<R> (&acc)[RPT][V]) {
+  using C = cx<R>;
+  constexpr int NIR = W + (AUX ? (V - 1) * WK : 0);
+  constexpr int NI = RPT * NIR;
+  constexpr int PD = V == 1 ? 6 : (V == 2 ? 3 : 2);
+  constexpr int NS = PD + 1;
+  C ring[NS][V];
+  C t[V];
+#pragma unroll
+  for (int it = 0; it < NI + PD; ++it) {
+    if (it < NI) {  // issue the gather of item `it`
+      const int r = it / NIR, q = it % NIR;
+      if (q < W) {
+        const C* p = src + (row[r] + a.off[q]) * V;
+#pragma unroll
+        for (int v = 0; v < V; ++v) ring[it % NS][v] = p[v];
+      } else {
+        const int v = 1 + (q - W) / WK, qq = (q - W) % WK;
+        const int kk = g0 + v - 1 < a.K ? g0 + v - 1 : 0;
+        ring[it % NS][0] = src[(row[r] + a.offk[kk][qq]) * V];
+      }
+    }
+    if (it >= PD) {  // consume item `it - PD`
+      const int c = it - PD;
+      const int r = c / NIR, q = c % NIR;
+      if (q == 0) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) t[v] = C{(R)0, (R)0};
+      }
+      if (q < W) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) cmac(t[v], bv[r][q], ring[c % NS][v]);
+      } else {
+        const int v = 1 + (q - W) / WK, qq = (q - W) % WK;
+        cmac(t[v], ek[v][r][qq], ring[c % NS][0]);
+      }
+      if (q == NIR - 1) {  // row complete
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          t[v].re *= inv;
+          t[v].im *= inv;
+          acc[r][v].re += t[v].re;
+          acc[r][v].im += t[v].im;
+        }
+        if (ok[r])
+#pragma unroll
+          for (int v = 0; v < V; ++v) dst[row[r] * V + v] = t[v];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// One application of (T_m(sgn*B))^s to the V vectors held in `acc`:
+//   t_0 = acc, t_j = (sgn B / j) t_{j-1}, acc += t_j   (Sec. III.B, eq. eBmpsi)
+// repeated s times (scaling and squaring, eq. scaling squaring).  With AUX,
+// vectors 1..V-1 are the top blocks X_k of the auxiliary vector (X_k; Y) with
+// Y = vector 0, i.e. t_j^X += (E_k/s / j) t_{j-1}^Y (eq. auxiliary equation).
+// blk0/blk1 point at block row 0 (after the halo); the block has V entries
+// per row.  Ends with a barrier, so the block may be rewritten right away.
+template <typename R, int RPT, int W, int V, int WK, bool AUX>
+__device__ __forceinline__ void taylor_block(cx<R>* blk0, cx<R>* blk1, const SweepArgs& a,
+                                             int g0, const int (&row)[RPT],
+                                             const bool (&ok)[RPT], const cx<R> (&bv)[RPT][W],
+                                             const cx<R> (&ek)[V][RPT][WK], int m, int s, R sgn,
+                                             cx<R> (&acc)[RPT][V]) {
+  using C = cx<R>;
+  for (int l = 0; l < s; ++l) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+      if (ok[r])
+#pragma unroll
+        for (int v = 0; v < V; ++v) blk0[row[r] * V + v] = acc[r][v];
+    __syncthreads();
+    const C* src = blk0;
+    C* dst = blk1;
+    for (int j = 1; j <= m; ++j) {
+      taylor_term<R, RPT, W, V, WK, AUX>(src, dst, a, g0, row, ok, bv, ek, sgn * inv_int<R>(j),
+                                         acc);
+      __syncthreads();
+      const C* tmp = src;
+      src = dst;
+      dst = const_cast<C*>(tmp);
+    }
+  }
+}
+
+template <typename R, int RPT>
+__device__ __forceinline__ void renormalise(cx<R> (&p)[RPT], double* red) {
+  double nv[1] = {0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) nv[0] += (double)p[r].re * p[r].re + (double)p[r].im * p[r].im;
+  block_sum<1>(nv, red);
+  const R sc = (R)(1.0 / sqrt(nv[0]));
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    p[r].re *= sc;
+    p[r].im *= sc;
+  }
+}
+
+// ---------------------------------------------------------------- forward ----
+// psi_n = (T_m(B_n))^s psi_{n-1} for n = 1..N (Sec. III.B, eq. eBmpsi);
+// penalty partial sum_n <psi_n|Omega|psi_n> (App. A, eq. c2st) and the overlap
+// <phi_T|psi_N> (Sec. III.A) of this column.
+template <typename R, int RPT, int W>
+__global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
+  using C = cx<R>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* red = reinterpret_cast<double*>(smem);
+  C* lds = reinterpret_cast<C*>(smem + kRedBytes);
+  const int d = a.d, tid = threadIdx.x, NT = blockDim.x;
+  const int h = blockIdx.x, b = blockIdx.y;
+  const size_t col0 = ((size_t)b * a.S + h) * d;
+  const int brow = block_rows(d, a.halo);
+  for (int i = tid; i < 2 * brow; i += NT) lds[i] = C{(R)0, (R)0};
+  C* const blk0 = lds + a.halo;
+  C* const blk1 = lds + brow + a.halo;
+
+  int row[RPT];
+  bool ok[RPT];
+  C acc[RPT][1];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = tid + r * NT;
+    ok[r] = i < d;
+    row[r] = ok[r] ? i : d - 1;
+    const double2 p = a.psi0[col0 + row[r]];
+    acc[r][0] = ok[r] ? C{(R)p.x, (R)p.y} : C{(R)0, (R)0};
+  }
+  __syncthreads();
+
+  C ek[1][RPT][1];
+  double pen = 0.0;
+  const double* ub = a.u + (size_t)b * a.K * a.N;
+  for (int n = 0; n < a.N; ++n) {
+    const int m = a.msch[(size_t)b * a.N + n];
+    const int s = a.ssch[(size_t)b * a.N + n];
+    C bv[RPT][W];
+    assemble_B<R, RPT, W>(a, ub, n, row, ok, a.dt / (double)s, bv);
+    taylor_block<R, RPT, W, 1, 1, false>(blk0, blk1, a, 0, row, ok, bv, ek, m, s, (R)1, acc);
+    if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
+      C p[RPT];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) p[r] = acc[r][0];
+      renormalise<R, RPT>(p, red);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) acc[r][0] = p[r];
+    }
+    if (a.omega) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (ok[r])
+          pen += a.omega[row[r]] *
+                 ((double)acc[r][0].re * acc[r][0].re + (double)acc[r][0].im * acc[r][0].im);
+    }
+  }
+
+  C* psiN = reinterpret_cast<C*>(a.psiN);
+  double v[3] = {0.0, 0.0, pen};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r)
+    if (ok[r]) {
+      psiN[col0 + row[r]] = acc[r][0];
+      const double2 t = a.tgt[col0 + row[r]];
+      const double pr = acc[r][0].re, pi = acc[r][0].im;
+      v[0] += t.x * pr + t.y * pi;  // Re conj(phi) psi
+      v[1] += t.x * pi - t.y * pr;  // Im conj(phi) psi
+    }
+  block_sum<3>(v, red);
+  if (tid == 0) {
+    a.ovl[((size_t)b * a.S + h) * 2 + 0] = v[0];
+    a.ovl[((size_t)b * a.S + h) * 2 + 1] = v[1];
+    a.pen[(size_t)b * a.S + h] = v[2];
+  }
+}
+
+// --------------------------------------------------------------- backward ----
+// For n = N..1 (kernel index n-1):
+//   psi_{n-1}   = (T_m(-B_n))^s psi_n           inverse propagation (Sec. III.C)
+//   Lambda'     = (T_m(-B_n))^s Lambda_n        co-state, U^dag = T(B^dag) = T(-B)
+//   (X_k; Y)    = (T_m(Aux_k/s))^s (0; psi_{n-1}), Aux_k = [[A, E_k],[0, A]]
+//                                                (Sec. III.B, eq. auxiliary equation)
+//   grad[k][n]  = 2 Re <Lambda_n | X_k>          (Sec. III.A, App. A)
+//   Lambda_{n-1} = Lambda' + (w_pen/(N S)) Omega psi_{n-1}   for n-1 >= 1 (App. A)
+// Controls are processed in groups of G (the bottom block Y is recomputed per
+// group) so that the (1+G)-vector double-buffered block fits in LDS.
+template <typename R, int RPT, int W, int WK, int G>
+__global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
+  using C = cx<R>;
+  constexpr int V2 = 1 + G;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* red = reinterpret_cast<double*>(smem);
+  C* lds = reinterpret_cast<C*>(smem + kRedBytes);
+  const int d = a.d, tid = threadIdx.x, NT = blockDim.x, K = a.K, N = a.N, S = a.S;
+  const int h = blockIdx.x, b = blockIdx.y;
+  const size_t col0 = ((size_t)b * S + h) * d;
+  const int brow = block_rows(d, a.halo);
+  constexpr int VMAX = V2 > 2 ? V2 : 2;
+  for (int i = tid; i < 2 * VMAX * brow; i += NT) lds[i] = C{(R)0, (R)0};
+  // phase 1 block: 2 vectors per row; phase 2 block: V2 vectors per row
+  C* const p1b0 = lds + 2 * a.halo;
+  C* const p1b1 = lds + 2 * brow + 2 * a.halo;
+  C* const p2b0 = lds + V2 * a.halo;
+  C* const p2b1 = lds + V2 * brow + V2 * a.halo;
+
+  C* cold = reinterpret_cast<C*>(a.cold) + ((size_t)b * S + h) * 3 * d;
+  C* const c_psi = cold;          // psi_{n-1}
+  C* const c_lam = cold + d;      // propagated co-state
+  C* const c_cur = cold + 2 * d;  // Lambda_n (for the overlaps)
+
+  int row[RPT];
+  bool ok[RPT];
+  C pl[RPT][2];  // psi and Lambda
+  const C* psiN = reinterpret_cast<const C*>(a.psiN);
+
+  // the turn: g, cost parts, Lambda_N = -(w_fid g/S) phi_T + (w_pen/(N S)) Omega psi_N
+  double gre = 0.0, gim = 0.0, ptot = 0.0;
+  for (int k = 0; k < S; ++k) {
+    gre += a.ovl[((size_t)b * S + k) * 2 + 0];
+    gim += a.ovl[((size_t)b * S + k) * 2 + 1];
+    ptot += a.pen[(size_t)b * S + k];
+  }
+  gre /= (double)S;
+  gim /= (double)S;
+  const double cpen = a.omega ? a.w_pen / ((double)N * S) : 0.0;
+  if (h == 0 && tid == 0) {
+    const double C1 = 1.0 - (gre * gre + gim * gim);
+    const double C2 = a.omega ? ptot / ((double)N * S) : 0.0;
+    a.res[(size_t)b * 8 + 0] = a.w_fid * C1 + (a.omega ? a.w_pen * C2 : 0.0);
+    a.res[(size_t)b * 8 + 1] = C1;
+    a.res[(size_t)b * 8 + 2] = C2;
+    a.res[(size_t)b * 8 + 3] = gre;
+    a.res[(size_t)b * 8 + 4] = gim;
+  }
+  const double fr = -a.w_fid * gre / S, fi = -a.w_fid * gim / S;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = tid + r * NT;
+    ok[r] = i < d;
+    row[r] = ok[r] ? i : d - 1;
+    const C p = psiN[col0 + row[r]];
+    const double2 t = a.tgt[col0 + row[r]];
+    const double w = a.omega ? a.omega[row[r]] : 0.0;
+    pl[r][0] = ok[r] ? p : C{(R)0, (R)0};
+    pl[r][1].re = ok[r] ? (R)(fr * t.x - fi * t.y + cpen * w * (double)p.re) : (R)0;
+    pl[r][1].im = ok[r] ? (R)(fr * t.y + fi * t.x + cpen * w * (double)p.im) : (R)0;
+  }
+  __syncthreads();
+
+  C ek1[2][RPT][1];
+  const double* ub = a.u + (size_t)b * K * N;
+  for (int n = N - 1; n >= 0; --n) {
+    const int m = a.msch[(size_t)b * N + n];
+    const int s = a.ssch[(size_t)b * N + n];
+    const double cs = a.dt / (double)s;
+    C bv[RPT][W];
+    assemble_B<R, RPT, W>(a, ub, n, row, ok, cs, bv);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+      if (ok[r]) c_cur[opaque(row[r])] = pl[r][1];
+
+    // phase 1: psi and Lambda through (T_m(-B))^s together
+    taylor_block<R, RPT, W, 2, 1, false>(p1b0, p1b1, a, 0, row, ok, bv, ek1, m, s, (R)-1, pl);
+    if (a.renorm_every > 0 && n % a.renorm_every == 0) {
+      C p[RPT];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) p[r] = pl[r][0];
+      renormalise<R, RPT>(p, red);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) pl[r][0] = p[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+      if (ok[r]) {
+        const int i = opaque(row[r]);
+        c_psi[i] = pl[r][0];
+        c_lam[i] = pl[r][1];
+      }
+
+    // phase 2: auxiliary actions, G controls per pass
+    for (int g0 = 0; g0 < K; g0 += G) {
+      C ek[V2][RPT][WK];
+#pragma unroll
+      for (int v = 1; v < V2; ++v) load_E<R, RPT, WK>(a, g0 + v - 1, g0 + v - 1 < K, row, ok, cs, ek[v]);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int q = 0; q < WK; ++q) ek[0][r][q] = C{(R)0, (R)0};
+      C yx[RPT][V2];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        yx[r][0] = ok[r] ? c_psi[opaque(row[r])] : C{(R)0, (R)0};
+#pragma unroll
+        for (int v = 1; v < V2; ++v) yx[r][v] = C{(R)0, (R)0};
+      }
+      taylor_block<R, RPT, W, V2, WK, true>(p2b0, p2b1, a, g0, row, ok, bv, ek, m, s, (R)1, yx);
+      double gv[G];
+#pragma unroll
+      for (int v = 0; v < G; ++v) gv[v] = 0.0;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (ok[r]) {
+          const C lc = c_cur[opaque(row[r])];
+#pragma unroll
+          for (int v = 0; v < G; ++v)
+            gv[v] += (double)lc.re * yx[r][v + 1].re + (double)lc.im * yx[r][v + 1].im;
+        }
+      block_sum<G>(gv, red);
+      if (tid == 0)
+        for (int v = 0; v < G && g0 + v < K; ++v)
+          a.gradp[(((size_t)b * S + h) * K + g0 + v) * N + n] = 2.0 * gv[v];
+    }
+
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = opaque(row[r]);
+      pl[r][0] = ok[r] ? c_psi[i] : C{(R)0, (R)0};
+      pl[r][1] = ok[r] ? c_lam[i] : C{(R)0, (R)0};
+      if (n >= 1 && a.omega && ok[r]) {
+        const double w = cpen * a.omega[i];
+        pl[r][1].re = (R)((double)pl[r][1].re + w * (double)pl[r][0].re);
+        pl[r][1].im = (R)((double)pl[r][1].im + w * (double)pl[r][0].im);
+      }
+    }
+  }
+
+  // drift of the rebuilt initial state
+  double dv[1] = {0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r)
+    if (ok[r]) {
+      const double2 p0 = a.psi0[col0 + row[r]];
+      const double dr = (double)pl[r][0].re - p0.x, di = (double)pl[r][0].im - p0.y;
+      dv[0] += dr * dr + di * di;
+    }
+  block_sum<1>(dv, red);
+  if (tid == 0) a.drift[(size_t)b * S + h] = sqrt(dv[0]);
+}
+
+}  // namespace hg

@@ -1,0 +1,213 @@
+// Launchers: step norms (App. C 1-norm), state norms, the sweep kernels and
+// the deterministic gradient reduction.  Kernel templates are instantiated
+// here for the supported (precision, rows per thread, union width, control
+// width) combinations; wider problems are rejected with HG_ERR_UNSUPPORTED.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "hg_internal.h"
+#include "sweep_kernels.h"
+#include "sweep_units.h"
+
+namespace hg {
+
+// theta[b][n] = dt * max_i sum_j |(H_0 + sum_k u[b][k][n] H_k)_ij| in FP64.
+// Row sums equal column sums because H_n is Hermitian (App. C, eq. norm
+// inequality and its footnote).  A non-finite amplitude yields a NaN norm.
+__global__ void __launch_bounds__(256) k_step_norms(const double2* vals, int W, int d, int K,
+                                                    const double* u, int N, double dt,
+                                                    double* theta) {
+  __shared__ double red[4];
+  const int n = blockIdx.x, b = blockIdx.y;
+  const double* ub = u + (size_t)b * K * N;
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) {
+    double rs = 0.0;
+    for (int e = 0; e < W; ++e) {
+      const double2 v0 = vals[(size_t)e * d + i];
+      double hr = v0.x, hi = v0.y;
+      for (int k = 0; k < K; ++k) {
+        const double c = ub[(size_t)k * N + n];
+        const double2 v = vals[((size_t)(k + 1) * W + e) * d + i];
+        hr = fma(c, v.x, hr);
+        hi = fma(c, v.y, hi);
+      }
+      rs += hypot(hr, hi);
+    }
+    mx = (rs > mx || rs != rs) ? rs : mx;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double t = __shfl_xor(mx, o, 64);
+    mx = (t > mx || t != t) ? t : mx;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = (red[w] > r || red[w] != red[w]) ? red[w] : r;
+    theta[(size_t)b * N + n] = dt * r;
+  }
+}
+
+// ||psi^h|| for every state of every batch entry (FP64).
+__global__ void __launch_bounds__(256) k_state_norms(const double2* psi, int d, int S,
+                                                     double* out) {
+  __shared__ double red[4];
+  const int h = blockIdx.x, b = blockIdx.y;
+  const double2* p = psi + ((size_t)b * S + h) * d;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) s += p[i].x * p[i].x + p[i].y * p[i].y;
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    out[(size_t)b * S + h] = sqrt(t);
+  }
+}
+
+// grad[b][k][n] = sum_h gradp[b][h][k][n], h ascending (deterministic).
+__global__ void __launch_bounds__(256) k_reduce_grad(const double* gradp, double* grad, int S,
+                                                     int KN, int B) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)B * KN) return;
+  const size_t b = idx / KN, kn = idx % KN;
+  double s = 0.0;
+  for (int h = 0; h < S; ++h) s += gradp[(b * S + h) * KN + kn];
+  grad[idx] = s;
+}
+
+hipError_t launch_step_norms(const DevOps& ops, int dim, int K, const double* u, int nb, int N,
+                             double dt, double* theta, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_norms, dim3(N, nb), dim3(256), 0, st, ops.vals, ops.W, dim, K, u, N,
+                     dt, theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_norms(const double* psi, int dim, int S, int nb, double* out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_state_norms, dim3(S, nb), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(psi), dim, S, out);
+  return hipGetLastError();
+}
+
+namespace {
+
+constexpr int kWidths[] = {3, 5, 9, 13};
+
+int width_template(int W) {
+  for (int w : kWidths)
+    if (W <= w) return w;
+  return -1;
+}
+
+size_t lds_bytes(int vec_per_row, int dim, int halo, size_t csize) {
+  return (size_t)kRedBytes + (size_t)2 * vec_per_row * block_rows(dim, halo) * csize;
+}
+
+}  // namespace
+
+bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_limit,
+                     SweepShape* sh, std::string* why) {
+  if (K > kMaxCtrl) {
+    *why = "more than " + std::to_string(kMaxCtrl) + " controls";
+    return false;
+  }
+  int rpt = (dim + kMaxThreads - 1) / kMaxThreads;
+  rpt = rpt <= 1 ? 1 : rpt <= 2 ? 2 : rpt <= 4 ? 4 : rpt <= 8 ? 8 : rpt;
+  if (rpt > kMaxRows) {
+    *why = "dimension " + std::to_string(dim) + " exceeds " +
+           std::to_string(kMaxRows * kMaxThreads) + " (rows per thread)";
+    return false;
+  }
+  if (width_template(ops.W) < 0) {
+    *why = "union pattern has " + std::to_string(ops.W) + " diagonals (max 13)";
+    return false;
+  }
+  const int rows = (dim + rpt - 1) / rpt;
+  const int threads = ((rows + 63) / 64) * 64;
+  const size_t cs = c128 ? 16 : 8;
+  const size_t fwd = lds_bytes(1, dim, ops.halo, cs);
+  if (fwd > lds_limit) {
+    *why = "forward term vectors need " + std::to_string(fwd) + " B of LDS";
+    return false;
+  }
+  // controls per backward pass: complex128 keeps one (register budget); complex64
+  // prefers a group size that divides K so no pass carries idle vectors
+  int G = 1;
+  if (!c128 && K >= 2) G = (K % 3 == 0) ? 3 : (K % 2 == 0) ? 2 : (K >= 3 ? 3 : 2);
+  auto bwd_bytes = [&](int g) { return lds_bytes(g + 1 > 2 ? g + 1 : 2, dim, ops.halo, cs); };
+  while (G > 1 && bwd_bytes(G) > lds_limit) --G;
+  if (bwd_bytes(G) > lds_limit) {
+    *why = "backward state block does not fit in LDS";
+    return false;
+  }
+  sh->dim = dim;
+  sh->n_ctrl = K;
+  sh->rows_per_thread = rpt;
+  sh->threads = threads;
+  sh->groups = G;
+  sh->lds_fwd = fwd;
+  sh->lds_bwd = bwd_bytes(G);
+  sh->c128 = c128;
+  return true;
+}
+
+hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuffers& bf,
+                        const SweepParams& p, hipStream_t st) {
+  SweepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.d = sh.dim;
+  a.K = sh.n_ctrl;
+  a.N = sh.n_steps;
+  a.S = sh.n_states;
+  a.W = ops.W;
+  a.halo = ops.halo;
+  a.G = sh.groups;
+  a.renorm_every = p.renorm_every;
+  for (int e = 0; e < kMaxDiag; ++e) a.off[e] = e < ops.W ? ops.off[e] : 0;
+  int wk = 1;
+  for (int k = 0; k < kMaxCtrl; ++k) {
+    a.WK[k] = k < sh.n_ctrl ? ops.WK[k] : 0;
+    if (k < sh.n_ctrl && ops.WK[k] > wk) wk = ops.WK[k];
+    for (int q = 0; q < kMaxDiagCtrl; ++q) a.offk[k][q] = (k < sh.n_ctrl && q < ops.WK[k]) ? ops.offk[k][q] : 0;
+  }
+  a.vals = ops.vals;
+  a.valk = ops.valk;
+  a.omega = ops.omega;
+  a.u = bf.u;
+  a.msch = bf.m_sched;
+  a.ssch = bf.s_sched;
+  a.psi0 = reinterpret_cast<const double2*>(bf.psi0);
+  a.tgt = reinterpret_cast<const double2*>(bf.targets);
+  a.psiN = bf.psiN;
+  a.cold = bf.cold;
+  a.ovl = bf.ovl;
+  a.pen = bf.pen;
+  a.gradp = bf.gradp;
+  a.drift = bf.drift;
+  a.res = bf.res;
+  a.dt = p.dt;
+  a.w_fid = p.w_fid;
+  a.w_pen = p.w_pen;
+  hipError_t e;
+  switch (width_template(ops.W)) {
+    case 3: e = run_width_3(a, sh, st, bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr); break;
+    case 5: e = run_width_5(a, sh, st, bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr); break;
+    case 9: e = run_width_9(a, sh, st, bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr); break;
+    default: e = run_width_13(a, sh, st, bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr); break;
+  }
+  if (e != hipSuccess) return e;
+  if (bf.grad && sh.n_ctrl > 0) {
+    const size_t total = (size_t)sh.n_batch * sh.n_ctrl * sh.n_steps;
+    hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       bf.gradp, bf.grad, sh.n_states, sh.n_ctrl * sh.n_steps, sh.n_batch);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace hg

@@ -1,0 +1,71 @@
+// Per-width translation units of the sweep kernels (sweep_w*.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hg_internal.h"
+#include "sweep_kernels.h"
+
+namespace hg {
+
+hipError_t run_width_3(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
+hipError_t run_width_5(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
+hipError_t run_width_9(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
+hipError_t run_width_13(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
+
+template <typename R, int RPT, int W, int WK, int G>
+hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream_t st,
+                             hipEvent_t* ev) {
+  auto fk = hg_forward<R, RPT, W>;
+  auto bk = hg_backward<R, RPT, W, WK, G>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fk),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_fwd);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(bk),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bwd);
+  if (e != hipSuccess) return e;
+  const dim3 grid(sh.n_states, sh.n_batch), block(sh.threads);
+  if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(fk, grid, block, sh.lds_fwd, st, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(bk, grid, block, sh.lds_bwd, st, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ev) e = hipEventRecord(ev[2], st);
+  return e;
+}
+
+// Dispatch on precision, rows per thread, control width and group size for a
+// fixed union width W.
+template <int W>
+hipError_t run_width(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev) {
+  int wk = 1;
+  for (int k = 0; k < a.K; ++k) wk = a.WK[k] > wk ? a.WK[k] : wk;
+#define HG_RUN(R, RPT, WKT, G) return run_sweep_kernels<R, RPT, W, WKT, G>(a, sh, st, ev)
+#define HG_BY_G_C64(RPT, WKT)           \
+  switch (sh.groups) {                  \
+    case 1: HG_RUN(float, RPT, WKT, 1); \
+    case 2: HG_RUN(float, RPT, WKT, 2); \
+    default: HG_RUN(float, RPT, WKT, 3); \
+  }
+#define HG_BY_WK(RPT)                                   \
+  if (sh.c128) {                                        \
+    if (wk <= 2) HG_RUN(double, RPT, 2, 1);             \
+    HG_RUN(double, RPT, 4, 1);                          \
+  }                                                     \
+  if (wk <= 2) { HG_BY_G_C64(RPT, 2) }                  \
+  HG_BY_G_C64(RPT, 4)
+  switch (sh.rows_per_thread) {
+    case 1: { HG_BY_WK(1) }
+    case 2: { HG_BY_WK(2) }
+    case 4: { HG_BY_WK(4) }
+    default: { HG_BY_WK(8) }
+  }
+#undef HG_BY_WK
+#undef HG_BY_G_C64
+#undef HG_RUN
+}
+
+}  // namespace hg

@@ -1,0 +1,9 @@
+// Sweep kernels instantiated for union width 5.
+#include "sweep_units.h"
+
+namespace hg {
+hipError_t run_width_5(const SweepArgs& a, const SweepShape& sh, hipStream_t st,
+                         hipEvent_t* ev) {
+  return run_width<5>(a, sh, st, ev);
+}
+}  // namespace hg

@@ -1,0 +1,90 @@
+"""Host-side checks of libhgrape (no GPU needed).
+
+The library loads, exports every function include/hgrape.h declares, and its
+host planner (FP64, Sec. III.B rule with the App. C bound) makes exactly the
+same integer decisions as the oracle planner on the same norms.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import planner as oplan
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hgrape.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2304_06200_amd import _lib
+    import ctypes
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in hgrape.h but not exported"
+    assert set(names) == set(_lib.EXPORTED)
+    assert _lib.hg_version() >= 100
+    assert _lib.hg_status_string(4) == "tolerance unreachable"
+
+
+def test_planner_matches_oracle_bitwise():
+    from paper_2304_06200_amd import _lib
+    rng = np.random.default_rng(7)
+    thetas = np.concatenate([rng.uniform(0.0, 30.0, 150), [0.0, 1e-9, 0.47, 10.3, 29.1, 41.0]])
+    for sigma in (3, 5, 9):
+        m, s = _lib.hg_plan(thetas, sigma, 1e-12, 2.0 ** -53)
+        for t, mm, ss in zip(thetas, m, s):
+            assert (int(mm), int(ss)) == oplan.select(float(t), sigma, 1e-12), (t, sigma)
+
+
+def test_planner_other_tolerances_and_roundoff():
+    from paper_2304_06200_amd import _lib
+    thetas = np.linspace(0.01, 60.0, 40)
+    for tau, u in ((1e-8, 2.0 ** -53), (1e-10, 2.0 ** -53), (1e-4, 2.0 ** -24)):
+        ok = []
+        for t in thetas:
+            try:
+                ok.append(oplan.select(float(t), 5, tau, u=u))
+            except ValueError:
+                break
+        if not ok:
+            continue
+        m, s = _lib.hg_plan(thetas[:len(ok)], 5, tau, u)
+        assert list(zip(m.tolist(), s.tolist())) == ok
+
+
+def test_error_bound_matches_oracle():
+    from paper_2304_06200_amd import _lib
+    rng = np.random.default_rng(8)
+    for _ in range(300):
+        t = float(rng.uniform(0, 40))
+        m = int(rng.integers(1, 61))
+        s = int(rng.integers(1, 40))
+        sig = int(rng.integers(1, 14))
+        a = _lib.hg_error_bound(t, m, s, sig, 2.0 ** -53)
+        b = oplan.error_bound(t, m, s, sig)
+        assert (a == b) or (np.isinf(a) and np.isinf(b)), (t, m, s, sig, a, b)
+
+
+def test_planner_errors():
+    from paper_2304_06200_amd import _lib
+    with pytest.raises(_lib.HGError) as e:
+        _lib.hg_plan(np.array([5.0]), 9, 1e-15, 2.0 ** -53)
+    assert e.value.status == _lib.HG_ERR_TOLERANCE_UNREACHABLE
+    assert "step 0" in str(e.value)
+    with pytest.raises(_lib.HGError) as e:
+        _lib.hg_plan(np.array([1.0, np.nan]), 9, 1e-12, 2.0 ** -53)
+    assert e.value.status == _lib.HG_ERR_NONFINITE
+    with pytest.raises(_lib.HGError) as e:
+        _lib.hg_plan(np.array([1.0]), 0, 1e-12, 2.0 ** -53)
+    assert e.value.status == _lib.HG_ERR_INVALID_ARG
+    m, s = _lib.hg_plan(np.array([], dtype=np.float64), 3, 1e-12, 2.0 ** -53)
+    assert m.size == 0

@@ -1,0 +1,142 @@
+"""GPU edge cases: degenerate sizes, batching, determinism and error paths."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from gpu_common import TOL, assert_parity, context, log, make_problem, run
+from workloads import make_config
+from workloads.circuits import Problem, destroy, haar_unitary
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(p):
+    from oracle import grape
+    return grape.cost_and_grad(p.H0, p.Hk, p.u, p.dt, p.psi0, p.targets, omega=p.omega,
+                               w_fid=p.w_fid, w_pen=p.w_pen)
+
+
+def _cavity_problem(d, K=2, N=20, S=2, seed=0, penalty=True, dt=0.3):
+    """Driven anharmonic oscillator with d levels (tridiagonal union pattern)."""
+    rng = np.random.default_rng(seed)
+    a = destroy(d) / np.sqrt(max(d, 1))       # bounded drive norm at any d
+    n = sp.diags(np.arange(d, dtype=float) / max(d, 1)).astype(complex)
+    H0 = sp.csr_matrix(sp.diags(rng.uniform(-2.0, 2.0, d)).astype(complex))
+    Hk = [sp.csr_matrix(a + a.conj().T), sp.csr_matrix(1j * (a.conj().T - a)),
+          sp.csr_matrix(n)][:K]
+    for h in Hk:
+        h.eliminate_zeros()
+    u = rng.uniform(-0.5, 0.5, (K, N))
+    psi0 = np.zeros((S, d), complex)
+    for h in range(S):
+        psi0[h, h % d] = 1.0
+    UT = haar_unitary(S, rng)
+    om = (np.arange(d) == d - 1).astype(float) if penalty else None
+    return Problem(f"osc{d}", sp.csr_matrix(H0), Hk, dt, u, psi0, UT.T @ psi0, om,
+                   w_fid=1.0, w_pen=0.5 if penalty else 0.0)
+
+
+@pytest.mark.parametrize("d", [1, 2, 63, 65, 513, 1031])
+def test_ragged_dimensions(d):
+    p = _cavity_problem(d, S=1 if d == 1 else 2, N=12)
+    log(f"[case] ragged d={d}")
+    for dt in ("c128", "c64"):
+        assert_parity(run(p, dt), _oracle(p), dt, label=f"osc{d}")
+
+
+def test_single_step_single_state_no_penalty():
+    p = _cavity_problem(10, K=1, N=1, S=1, penalty=False)
+    log("[case] N=1 S=1 K=1 no penalty")
+    assert_parity(run(p, "c128"), _oracle(p), "c128", label="N1")
+
+
+def test_no_controls():
+    """K = 0: cost only (the drift alone); the library returns no gradient."""
+    p = _cavity_problem(12, K=1, N=5, S=2)
+    p0 = Problem("drift-only", p.H0, [], p.dt, np.zeros((0, 5)), p.psi0, p.targets, p.omega,
+                 w_fid=1.0, w_pen=0.5)
+    log("[case] K=0")
+    r = run(p0, "c128")
+    from oracle import grape
+    ref = grape.cost_and_grad(p0.H0, [], np.zeros((0, 5)), p0.dt, p0.psi0, p0.targets,
+                              omega=p0.omega, w_fid=1.0, w_pen=0.5)
+    assert abs(r.cost[0] - ref["cost"]) <= 1e-10 * abs(ref["cost"])
+    assert r.grad is None
+
+
+def test_number_operator_control_one_diagonal():
+    p = _cavity_problem(30, K=3, N=15, S=3)
+    log("[case] K=3 with a diagonal control")
+    for dt in ("c128", "c64"):
+        assert_parity(run(p, dt), _oracle(p), dt, label="ndiag")
+
+
+def test_batch_equals_single_bitwise():
+    p = make_config("cfg2", N=50, d_c=12)
+    prob = make_problem(p)
+    rng = np.random.default_rng(5)
+    us = np.stack([p.u, p.u + 0.01 * rng.standard_normal(p.u.shape), -p.u])
+    log("[case] batch of 3 vs singles")
+    for dt in ("c128", "c64"):
+        rb = run(p, dt, prob=prob, batch_u=us)
+        for b in range(3):
+            r1 = run(p, dt, prob=prob, batch_u=us[b])
+            assert r1.cost[0] == rb.cost[b]
+            assert np.array_equal(r1.grad[0].cpu().numpy(), rb.grad[b].cpu().numpy())
+
+
+def test_repeatable_bitwise():
+    p = make_config("cfg3", N=4, d_c=30)
+    prob = make_problem(p)
+    log("[case] repeatability")
+    a = run(p, "c64", prob=prob)
+    b = run(p, "c64", prob=prob)
+    assert a.cost[0] == b.cost[0]
+    assert np.array_equal(a.grad.cpu().numpy(), b.grad.cpu().numpy())
+
+
+def test_drift_reported_and_small():
+    p = make_config("cfg2", N=200)
+    r128 = run(p, "c128")
+    r64 = run(p, "c64")
+    log(f"[case] drift c128 {r128.drift[0]:.2e} c64 {r64.drift[0]:.2e}")
+    assert r128.drift[0] < 1e-11
+    assert r64.drift[0] < 1e-3
+
+
+def test_error_paths():
+    import torch
+    import paper_2304_06200_amd as hg
+    from paper_2304_06200_amd import _lib as L
+    p = make_config("cfg2", N=10, d_c=6)
+    prob = make_problem(p)
+    u, psi0, tg = (torch.tensor(p.u, device="cuda"),
+                   torch.tensor(p.psi0, dtype=torch.complex128, device="cuda"),
+                   torch.tensor(p.targets, dtype=torch.complex128, device="cuda"))
+    log("[case] error paths")
+    with pytest.raises(L.HGError) as e:
+        hg.evaluate(prob, u, 2 * psi0, tg, p.dt)
+    assert e.value.status == L.HG_ERR_INVALID_ARG
+    bad = u.clone()
+    bad[1, 3] = float("nan")
+    with pytest.raises(L.HGError) as e:
+        hg.evaluate(prob, bad, psi0, tg, p.dt)
+    assert e.value.status == L.HG_ERR_NONFINITE
+    with pytest.raises(L.HGError) as e:
+        hg.evaluate(prob, u, psi0, tg, p.dt, tau=1e-16)
+    assert e.value.status == L.HG_ERR_TOLERANCE_UNREACHABLE
+    with pytest.raises(L.HGError) as e:
+        hg.evaluate(prob, u, psi0, tg, -1.0)
+    assert e.value.status == L.HG_ERR_INVALID_ARG
+    nh = sp.csr_matrix(np.triu(np.ones((6, 6))) * (1 + 1j))
+    with pytest.raises(L.HGError) as e:
+        hg.Problem(context(), nh, [], None)
+    assert e.value.status == L.HG_ERR_NOT_HERMITIAN
+    # a union pattern with too many diagonals is rejected cleanly
+    dense = sp.csr_matrix(np.ones((40, 40), complex))
+    with pytest.raises(L.HGError) as e:
+        hg.Problem(context(), dense, [], None)
+    assert e.value.status == L.HG_ERR_UNSUPPORTED
+    # the evaluation still works after the errors
+    r = hg.evaluate(prob, u, psi0, tg, p.dt)
+    assert np.isfinite(r.cost[0])
