@@ -13,9 +13,16 @@
 // tail is summed directly until a term drops below 1e-18 of the sum; the
 // rounding part is evaluated as alpha^s expm1(s log1p(beta/alpha)); s runs
 // 1, 2, ... up to floor(tau / gamma_3), m runs 1..60, first hit wins.
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <limits>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
 
 namespace hg {
 
@@ -100,24 +107,129 @@ static int select_one(double theta, int sigma, double tau, double u, int32_t* m_
   return capped ? 2 : 1;
 }
 
+namespace {
+
+// Feasibility thresholds for fixed (sigma, tau, u): th[s][m] is the largest
+// norm theta with E_A(m, s, theta) <= tau (negative if none), found by
+// bisection on the same floating-point function the direct search uses.
+// Because E_A grows with theta, "E_A(m, s, theta) <= tau" is "theta <= th[s][m]"
+// except within rounding noise of the threshold; lookups that land within
+// 1e-12 (relative) of any deciding threshold fall back to the direct search,
+// so every decision equals the direct search's.
+struct Thresholds {
+  int sigma = 0;
+  double tau = 0.0, u = 0.0;
+  std::vector<std::array<double, 61>> th;  // index s (1-based), m (1..60)
+  std::vector<double> smax;                // max_m th[s][m]
+  int64_t s_lim = 0;
+  bool capped = false;
+
+  double threshold(int m, int s) const {
+    if (!(error_bound(0.0, m, s, sigma, u) <= tau)) return -1.0;
+    double lo = 0.0, hi = 1.0;
+    while (error_bound(hi, m, s, sigma, u) <= tau) {
+      lo = hi;
+      hi *= 2.0;
+      if (hi > 1e12) return lo;
+    }
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (error_bound(mid, m, s, sigma, u) <= tau) lo = mid; else hi = mid;
+    }
+    return lo;
+  }
+
+  // make sure rows 1..s exist
+  void extend(int64_t s) {
+    if (th.empty()) {
+      th.resize(1);
+      smax.assign(1, -1.0);
+    }
+    while ((int64_t)th.size() <= s) {
+      const int ss = (int)th.size();
+      std::array<double, 61> row;
+      row[0] = -1.0;
+      double mx = -1.0;
+      const double up = u_prime(u);
+      for (int m = 1; m <= 60; ++m) {
+        // beta at theta = 0 is gamma_{m+2}; once s*gamma_{m+2} > 2 tau no larger m is feasible
+        if ((double)ss * gamma_n(m + 2, up) > 2.0 * tau) {
+          for (int mm = m; mm <= 60; ++mm) row[mm] = -1.0;
+          break;
+        }
+        row[m] = threshold(m, ss);
+        mx = std::max(mx, row[m]);
+      }
+      th.push_back(row);
+      smax.push_back(mx);
+    }
+  }
+};
+
+std::mutex g_tab_mu;
+std::map<std::tuple<int, double, double>, std::shared_ptr<Thresholds>> g_tabs;
+
+std::shared_ptr<Thresholds> table_for(int sigma, double tau, double u) {
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  auto key = std::make_tuple(sigma, tau, u);
+  auto it = g_tabs.find(key);
+  if (it != g_tabs.end()) return it->second;
+  auto t = std::make_shared<Thresholds>();
+  t->sigma = sigma;
+  t->tau = tau;
+  t->u = u;
+  const double g3 = gamma_n(3, u_prime(u));
+  t->s_lim = std::max<int64_t>(1, (int64_t)(tau / g3));
+  t->capped = t->s_lim > kSCap;
+  if (t->capped) t->s_lim = kSCap;
+  g_tabs[key] = t;
+  return t;
+}
+
+bool near(double a, double b) { return b >= 0.0 && std::fabs(a - b) <= 1e-12 * std::max(a, b); }
+
+}  // namespace
+
 int plan_steps(const double* theta, int64_t n, int sigma, double tau, double u, int32_t* m_out,
                int32_t* s_out, int64_t* fail_index) {
-  double last_theta = std::numeric_limits<double>::quiet_NaN();
-  int32_t last_m = 0, last_s = 0;
+  std::shared_ptr<Thresholds> tab = table_for(sigma, tau, u);
+  std::lock_guard<std::mutex> lk(g_tab_mu);  // the table grows lazily
   for (int64_t i = 0; i < n; ++i) {
-    if (theta[i] == last_theta) {  // identical norm: identical choice
-      m_out[i] = last_m;
-      s_out[i] = last_s;
+    const double t = theta[i];
+    // smallest s whose best threshold admits t, growing the table as needed
+    int64_t s = 1;
+    bool found = false;
+    for (; s <= tab->s_lim; ++s) {
+      tab->extend(s);
+      if (t <= tab->smax[s]) {
+        found = true;
+        break;
+      }
+    }
+    bool exact = found;
+    int m = 0;
+    if (found) {
+      for (m = 1; m <= 60; ++m)
+        if (t <= tab->th[s][m]) break;
+      // decisions made close to a threshold are re-taken by the direct search
+      for (int64_t s2 = 1; s2 <= s && exact; ++s2)
+        for (int m2 = 1; m2 <= 60; ++m2)
+          if (near(t, tab->th[s2][m2])) {
+            exact = false;
+            break;
+          }
+    }
+    if (exact) {
+      m_out[i] = m;
+      s_out[i] = (int32_t)s;
       continue;
     }
-    const int rc = select_one(theta[i], sigma, tau, u, &m_out[i], &s_out[i]);
+    const int rc = select_one(t, sigma, tau, u, &m_out[i], &s_out[i]);
     if (rc != 0) {
       *fail_index = i;
       return rc;
     }
-    last_theta = theta[i];
-    last_m = m_out[i];
-    last_s = s_out[i];
   }
   return 0;
 }

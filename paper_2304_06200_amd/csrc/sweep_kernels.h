@@ -55,9 +55,6 @@ struct SweepArgs {
   double dt, w_fid, w_pen;
 };
 
-// Rows of the LDS state block: [halo zero rows][d rows][halo zero rows].
-__host__ __device__ inline int block_rows(int d, int halo) { return d + 2 * halo; }
-
 template <typename R>
 __device__ __forceinline__ void cmac(cx<R>& acc, const cx<R>& a, const cx<R>& b) {
   acc.re = fma(a.re, b.re, acc.re);
@@ -71,6 +68,12 @@ __device__ __forceinline__ void cmac(cx<R>& acc, const cx<R>& a, const cx<R>& b)
 // (which would pin one 64-bit address per operator entry in registers).
 __device__ __forceinline__ int opaque(int x) {
   asm volatile("" : "+v"(x));
+  return x;
+}
+// The same for a wave-uniform value kept in a scalar register: the compiler
+// then adds it with one scalar op instead of splitting it into vector adds.
+__device__ __forceinline__ uint32_t opaque_s(uint32_t x) {
+  asm volatile("" : "+s"(x));
   return x;
 }
 
@@ -172,39 +175,118 @@ __device__ __forceinline__ float inv_int<float>(int j) { return kInvF[j]; }
 template <>
 __device__ __forceinline__ double inv_int<double>(int j) { return kInvD[j]; }
 
-// One Taylor term for the V vectors of this thread's rows:
+// ---------------------------------------------------------- LDS state block --
+// A double-buffered block of V vectors is stored as planes of 16-byte rows:
+// a plane row holds VP = 16/sizeof(complex) vectors of one matrix row (two
+// complex64 or one complex128; a single complex64 vector uses 8-byte rows).
+// Consecutive lanes own consecutive rows, so one ds_read of a plane row per
+// (row, diagonal) is a contiguous, bank-conflict-free wave access.  Planes of
+// a buffer are PS rows apart, PS = RPT * 512 (the largest dimension for that
+// row count), a compile-time constant, so plane offsets fold into the
+// instruction's immediate offset.  Reads at row + off outside [0, d) land in
+// a neighbouring plane or in a zeroed guard of `halo` rows before the first and
+// after the last plane: finite data times a zero coefficient (the operator
+// diagonals are zero outside the matrix), so no bounds tests are needed.
+// Plane stride in rows: RPT * 512 when RPT <= 4 (a compile-time constant, so
+// plane offsets become immediates), else the dimension itself (runtime).
+__host__ __device__ constexpr int plane_rows(int rpt, int d) { return rpt <= 4 ? rpt * kMaxThreads : d; }
+__host__ __device__ constexpr int block_vp(int cs, int v) { return (16 / cs) < v ? (16 / cs) : v; }
+// Bytes of LDS of a double-buffered block of v vectors (both guards included).
+__host__ __device__ constexpr int block_bytes(int cs, int rpt, int v, int d, int halo) {
+  return 2 * ((v + block_vp(cs, v) - 1) / block_vp(cs, v)) * plane_rows(rpt, d) *
+             (block_vp(cs, v) * cs) +
+         2 * halo * block_vp(cs, v) * cs;
+}
+
+template <typename R, int RPT, int V>
+struct Blk {
+  static constexpr int CS = (int)sizeof(cx<R>);
+  static constexpr int VP = block_vp(CS, V);
+  static constexpr int NP = (V + VP - 1) / VP;
+  static constexpr int RB = VP * CS;                 // bytes per plane row
+  static constexpr bool CPS = RPT <= 4;              // compile-time plane stride?
+  static constexpr int PSC = RPT * kMaxThreads * RB;  // that stride in bytes
+  __device__ static uint32_t ps(int d) { return CPS ? (uint32_t)PSC : (uint32_t)d * RB; }
+  __device__ static uint32_t bs(int d) { return NP * ps(d); }
+  __device__ static int bytes(int d, int halo) { return block_bytes(CS, RPT, V, d, halo); }
+  struct alignas(RB) Row {
+    cx<R> v[VP];
+  };
+};
+
+extern __shared__ __align__(16) unsigned char hg_smem[];
+
+template <typename T>
+__device__ __forceinline__ T lds_ld(uint32_t off) {
+  return *reinterpret_cast<const T*>(hg_smem + off);
+}
+template <typename T>
+__device__ __forceinline__ void lds_st(uint32_t off, const T& v) {
+  *reinterpret_cast<T*>(hg_smem + off) = v;
+}
+
+// Write the V accumulators of this thread's rows into buffer 0 of the block.
+template <typename R, int RPT, int V>
+__device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t (&rowb)[RPT],
+                                            const bool (&ok)[RPT], const cx<R> (&acc)[RPT][V]) {
+  using L = Blk<R, RPT, V>;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r)
+    if (ok[r])
+#pragma unroll
+      for (int p = 0; p < L::NP; ++p) {
+        typename L::Row w;
+#pragma unroll
+        for (int q = 0; q < L::VP; ++q) w.v[q] = (p * L::VP + q < V) ? acc[r][p * L::VP + q] : cx<R>{(R)0, (R)0};
+        lds_st(base + rowb[r] + p * L::ps(d), w);
+      }
+}
+
+// One Taylor term for the V vectors of this thread's rows, reading buffer
+// SRC1 and writing the other one:
 //   t^v = sgn/j * (sum_e B[r][e] src^v[row + off_e]  (+ E_k/s src^Y[row + offk] for AUX tops))
 //   acc += t ; dst = t
 // The gathers are software-pipelined: a ring of PD+1 register slots keeps PD
 // LDS reads in flight ahead of the FMAs that consume them, and a scheduling
 // barrier after each item pins that order.  Items run row by row: first the W
-// union diagonals (a V-wide read each), then for AUX the (V-1)*WK derivative
-// operand reads (the Y entry only).
-template <typename R, int RPT, int W, int V, int WK, bool AUX>
-__device__ __forceinline__ void taylor_term(const cx<R>* src, cx<R>* dst, const SweepArgs& a,
-                                            int g0, const int (&row)[RPT], const bool (&ok)[RPT],
+// union diagonals (NP plane-row reads each), then for AUX the (V-1)*WK
+// derivative operand reads (the Y entry only).  Single-vector blocks keep all
+// RPT*W gather addresses in registers (computed once per kernel); multi-vector
+// blocks rebuild each from one per-row base with one add, which keeps the
+// register budget for the extra accumulators.
+template <typename R, int RPT, int W, int V, int WK, bool AUX, bool SRC1>
+__device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, int g0,
+                                            const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                             const cx<R> (&bv)[RPT][W],
                                             const cx<R> (&ek)[V][RPT][WK], R inv,
                                             cx<R> (&acc)[RPT][V]) {
   using C = cx<R>;
+  using L = Blk<R, RPT, V>;
+  using Row = typename L::Row;
   constexpr int NIR = W + (AUX ? (V - 1) * WK : 0);
   constexpr int NI = RPT * NIR;
-  constexpr int PD = V == 1 ? 6 : (V == 2 ? 3 : 2);
+  constexpr int PD = V == 1 ? (sizeof(R) == 4 ? 6 : 3) : (V == 2 && sizeof(R) == 4 ? 3 : 2);
   constexpr int NS = PD + 1;
-  C ring[NS][V];
+  const int d = a.d;
+  const uint32_t SRC = SRC1 ? L::bs(d) : 0, DST = SRC1 ? 0 : L::bs(d);
+  Row ring[NS][L::NP];
   C t[V];
+  uint32_t rb[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) rb[r] = V > 1 ? (uint32_t)opaque((int)rowb[r]) : rowb[r];
 #pragma unroll
   for (int it = 0; it < NI + PD; ++it) {
     if (it < NI) {  // issue the gather of item `it`
       const int r = it / NIR, q = it % NIR;
       if (q < W) {
-        const C* p = src + (row[r] + a.off[q]) * V;
+        const uint32_t ad = rb[r] + opaque_s((uint32_t)(a.off[q] * L::RB) + base + SRC);
 #pragma unroll
-        for (int v = 0; v < V; ++v) ring[it % NS][v] = p[v];
+        for (int p = 0; p < L::NP; ++p) ring[it % NS][p] = lds_ld<Row>(ad + p * L::ps(d));
       } else {
         const int v = 1 + (q - W) / WK, qq = (q - W) % WK;
         const int kk = g0 + v - 1 < a.K ? g0 + v - 1 : 0;
-        ring[it % NS][0] = src[(row[r] + a.offk[kk][qq]) * V];
+        ring[it % NS][0].v[0] =
+            lds_ld<C>(rb[r] + opaque_s((uint32_t)(a.offk[kk][qq] * L::RB) + base + SRC));
       }
     }
     if (it >= PD) {  // consume item `it - PD`
@@ -216,10 +298,10 @@ __device__ __forceinline__ void taylor_term(const cx<R>* src, cx<R>* dst, const 
       }
       if (q < W) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) cmac(t[v], bv[r][q], ring[c % NS][v]);
+        for (int v = 0; v < V; ++v) cmac(t[v], bv[r][q], ring[c % NS][v / L::VP].v[v % L::VP]);
       } else {
         const int v = 1 + (q - W) / WK, qq = (q - W) % WK;
-        cmac(t[v], ek[v][r][qq], ring[c % NS][0]);
+        cmac(t[v], ek[v][r][qq], ring[c % NS][0].v[0]);
       }
       if (q == NIR - 1) {  // row complete
 #pragma unroll
@@ -231,7 +313,13 @@ __device__ __forceinline__ void taylor_term(const cx<R>* src, cx<R>* dst, const 
         }
         if (ok[r])
 #pragma unroll
-          for (int v = 0; v < V; ++v) dst[row[r] * V + v] = t[v];
+          for (int p = 0; p < L::NP; ++p) {
+            Row w;
+#pragma unroll
+            for (int qv = 0; qv < L::VP; ++qv)
+              w.v[qv] = (p * L::VP + qv < V) ? t[p * L::VP + qv] : C{(R)0, (R)0};
+            lds_st(rb[r] + opaque_s(base + DST) + p * L::ps(d), w);
+          }
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -243,31 +331,27 @@ __device__ __forceinline__ void taylor_term(const cx<R>* src, cx<R>* dst, const 
 // repeated s times (scaling and squaring, eq. scaling squaring).  With AUX,
 // vectors 1..V-1 are the top blocks X_k of the auxiliary vector (X_k; Y) with
 // Y = vector 0, i.e. t_j^X += (E_k/s / j) t_{j-1}^Y (eq. auxiliary equation).
-// blk0/blk1 point at block row 0 (after the halo); the block has V entries
-// per row.  Ends with a barrier, so the block may be rewritten right away.
+// `base` is the byte offset of buffer 0, plane 0, row 0.  The term loop is
+// unrolled by two so the buffer being read is a compile-time choice.  Ends
+// with a barrier, so the block may be rewritten right away.
 template <typename R, int RPT, int W, int V, int WK, bool AUX>
-__device__ __forceinline__ void taylor_block(cx<R>* blk0, cx<R>* blk1, const SweepArgs& a,
-                                             int g0, const int (&row)[RPT],
+__device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, int g0,
+                                             const uint32_t (&rowb)[RPT],
                                              const bool (&ok)[RPT], const cx<R> (&bv)[RPT][W],
                                              const cx<R> (&ek)[V][RPT][WK], int m, int s, R sgn,
                                              cx<R> (&acc)[RPT][V]) {
-  using C = cx<R>;
   for (int l = 0; l < s; ++l) {
-#pragma unroll
-    for (int r = 0; r < RPT; ++r)
-      if (ok[r])
-#pragma unroll
-        for (int v = 0; v < V; ++v) blk0[row[r] * V + v] = acc[r][v];
+    block_store<R, RPT, V>(base, a.d, rowb, ok, acc);
     __syncthreads();
-    const C* src = blk0;
-    C* dst = blk1;
-    for (int j = 1; j <= m; ++j) {
-      taylor_term<R, RPT, W, V, WK, AUX>(src, dst, a, g0, row, ok, bv, ek, sgn * inv_int<R>(j),
-                                         acc);
+    for (int j = 1; j <= m; j += 2) {
+      taylor_term<R, RPT, W, V, WK, AUX, false>(base, a, g0, rowb, ok, bv, ek,
+                                                sgn * inv_int<R>(j), acc);
       __syncthreads();
-      const C* tmp = src;
-      src = dst;
-      dst = const_cast<C*>(tmp);
+      if (j + 1 <= m) {
+        taylor_term<R, RPT, W, V, WK, AUX, true>(base, a, g0, rowb, ok, bv, ek,
+                                                 sgn * inv_int<R>(j + 1), acc);
+        __syncthreads();
+      }
     }
   }
 }
@@ -293,18 +377,19 @@ __device__ __forceinline__ void renormalise(cx<R> (&p)[RPT], double* red) {
 template <typename R, int RPT, int W>
 __global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
   using C = cx<R>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* red = reinterpret_cast<double*>(smem);
-  C* lds = reinterpret_cast<C*>(smem + kRedBytes);
+  using L = Blk<R, RPT, 1>;
+  double* red = reinterpret_cast<double*>(hg_smem);
   const int d = a.d, tid = threadIdx.x, NT = blockDim.x;
   const int h = blockIdx.x, b = blockIdx.y;
   const size_t col0 = ((size_t)b * a.S + h) * d;
-  const int brow = block_rows(d, a.halo);
-  for (int i = tid; i < 2 * brow; i += NT) lds[i] = C{(R)0, (R)0};
-  C* const blk0 = lds + a.halo;
-  C* const blk1 = lds + brow + a.halo;
+  {
+    uint32_t* z = reinterpret_cast<uint32_t*>(hg_smem + kRedBytes);
+    for (int i = tid; i < L::bytes(d, a.halo) / 4; i += NT) z[i] = 0u;
+  }
+  const uint32_t base = kRedBytes + a.halo * L::RB;
 
   int row[RPT];
+  uint32_t rowb[RPT];
   bool ok[RPT];
   C acc[RPT][1];
 #pragma unroll
@@ -312,6 +397,7 @@ __global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
     const int i = tid + r * NT;
     ok[r] = i < d;
     row[r] = ok[r] ? i : d - 1;
+    rowb[r] = (uint32_t)row[r] * L::RB;
     const double2 p = a.psi0[col0 + row[r]];
     acc[r][0] = ok[r] ? C{(R)p.x, (R)p.y} : C{(R)0, (R)0};
   }
@@ -325,7 +411,7 @@ __global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
     const int s = a.ssch[(size_t)b * a.N + n];
     C bv[RPT][W];
     assemble_B<R, RPT, W>(a, ub, n, row, ok, a.dt / (double)s, bv);
-    taylor_block<R, RPT, W, 1, 1, false>(blk0, blk1, a, 0, row, ok, bv, ek, m, s, (R)1, acc);
+    taylor_block<R, RPT, W, 1, 1, false>(base, a, 0, rowb, ok, bv, ek, m, s, (R)1, acc);
     if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
       C p[RPT];
 #pragma unroll
@@ -376,20 +462,21 @@ template <typename R, int RPT, int W, int WK, int G>
 __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
   using C = cx<R>;
   constexpr int V2 = 1 + G;
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* red = reinterpret_cast<double*>(smem);
-  C* lds = reinterpret_cast<C*>(smem + kRedBytes);
+  using L1 = Blk<R, RPT, 2>;
+  using L2 = Blk<R, RPT, V2>;
+  double* red = reinterpret_cast<double*>(hg_smem);
   const int d = a.d, tid = threadIdx.x, NT = blockDim.x, K = a.K, N = a.N, S = a.S;
   const int h = blockIdx.x, b = blockIdx.y;
   const size_t col0 = ((size_t)b * S + h) * d;
-  const int brow = block_rows(d, a.halo);
-  constexpr int VMAX = V2 > 2 ? V2 : 2;
-  for (int i = tid; i < 2 * VMAX * brow; i += NT) lds[i] = C{(R)0, (R)0};
-  // phase 1 block: 2 vectors per row; phase 2 block: V2 vectors per row
-  C* const p1b0 = lds + 2 * a.halo;
-  C* const p1b1 = lds + 2 * brow + 2 * a.halo;
-  C* const p2b0 = lds + V2 * a.halo;
-  C* const p2b1 = lds + V2 * brow + V2 * a.halo;
+  {
+    const int nb1 = L1::bytes(d, a.halo), nb2 = L2::bytes(d, a.halo);
+    const int nb = nb1 > nb2 ? nb1 : nb2;
+    uint32_t* z = reinterpret_cast<uint32_t*>(hg_smem + kRedBytes);
+    for (int i = tid; i < nb / 4; i += NT) z[i] = 0u;
+  }
+  // phase 1 block (psi, Lambda) and phase 2 block (Y, X_1..X_G) share the region
+  const uint32_t base1 = kRedBytes + a.halo * L1::RB;
+  const uint32_t base2 = kRedBytes + a.halo * L2::RB;
 
   C* cold = reinterpret_cast<C*>(a.cold) + ((size_t)b * S + h) * 3 * d;
   C* const c_psi = cold;          // psi_{n-1}
@@ -397,6 +484,7 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
   C* const c_cur = cold + 2 * d;  // Lambda_n (for the overlaps)
 
   int row[RPT];
+  uint32_t rowb1[RPT], rowb2[RPT];
   bool ok[RPT];
   C pl[RPT][2];  // psi and Lambda
   const C* psiN = reinterpret_cast<const C*>(a.psiN);
@@ -426,6 +514,8 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
     const int i = tid + r * NT;
     ok[r] = i < d;
     row[r] = ok[r] ? i : d - 1;
+    rowb1[r] = (uint32_t)row[r] * L1::RB;
+    rowb2[r] = (uint32_t)row[r] * L2::RB;
     const C p = psiN[col0 + row[r]];
     const double2 t = a.tgt[col0 + row[r]];
     const double w = a.omega ? a.omega[row[r]] : 0.0;
@@ -448,7 +538,7 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
       if (ok[r]) c_cur[opaque(row[r])] = pl[r][1];
 
     // phase 1: psi and Lambda through (T_m(-B))^s together
-    taylor_block<R, RPT, W, 2, 1, false>(p1b0, p1b1, a, 0, row, ok, bv, ek1, m, s, (R)-1, pl);
+    taylor_block<R, RPT, W, 2, 1, false>(base1, a, 0, rowb1, ok, bv, ek1, m, s, (R)-1, pl);
     if (a.renorm_every > 0 && n % a.renorm_every == 0) {
       C p[RPT];
 #pragma unroll
@@ -481,7 +571,7 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
 #pragma unroll
         for (int v = 1; v < V2; ++v) yx[r][v] = C{(R)0, (R)0};
       }
-      taylor_block<R, RPT, W, V2, WK, true>(p2b0, p2b1, a, g0, row, ok, bv, ek, m, s, (R)1, yx);
+      taylor_block<R, RPT, W, V2, WK, true>(base2, a, g0, rowb2, ok, bv, ek, m, s, (R)1, yx);
       double gv[G];
 #pragma unroll
       for (int v = 0; v < G; ++v) gv[v] = 0.0;

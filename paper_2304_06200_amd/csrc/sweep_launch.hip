@@ -4,6 +4,7 @@
 // width) combinations; wider problems are rejected with HG_ERR_UNSUPPORTED.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -104,8 +105,8 @@ int width_template(int W) {
   return -1;
 }
 
-size_t lds_bytes(int vec_per_row, int dim, int halo, size_t csize) {
-  return (size_t)kRedBytes + (size_t)2 * vec_per_row * block_rows(dim, halo) * csize;
+size_t lds_bytes(int vecs, int rpt, int dim, int halo, size_t csize) {
+  return (size_t)kRedBytes + (size_t)block_bytes((int)csize, rpt, vecs, dim, halo);
 }
 
 }  // namespace
@@ -117,7 +118,7 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
     return false;
   }
   int rpt = (dim + kMaxThreads - 1) / kMaxThreads;
-  rpt = rpt <= 1 ? 1 : rpt <= 2 ? 2 : rpt <= 4 ? 4 : rpt <= 8 ? 8 : rpt;
+  rpt = rpt <= 4 ? rpt : rpt <= 6 ? 6 : 8;
   if (rpt > kMaxRows) {
     *why = "dimension " + std::to_string(dim) + " exceeds " +
            std::to_string(kMaxRows * kMaxThreads) + " (rows per thread)";
@@ -130,7 +131,7 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
   const int rows = (dim + rpt - 1) / rpt;
   const int threads = ((rows + 63) / 64) * 64;
   const size_t cs = c128 ? 16 : 8;
-  const size_t fwd = lds_bytes(1, dim, ops.halo, cs);
+  const size_t fwd = lds_bytes(1, rpt, dim, ops.halo, cs);
   if (fwd > lds_limit) {
     *why = "forward term vectors need " + std::to_string(fwd) + " B of LDS";
     return false;
@@ -139,7 +140,9 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
   // prefers a group size that divides K so no pass carries idle vectors
   int G = 1;
   if (!c128 && K >= 2) G = (K % 3 == 0) ? 3 : (K % 2 == 0) ? 2 : (K >= 3 ? 3 : 2);
-  auto bwd_bytes = [&](int g) { return lds_bytes(g + 1 > 2 ? g + 1 : 2, dim, ops.halo, cs); };
+  auto bwd_bytes = [&](int g) {
+    return std::max(lds_bytes(2, rpt, dim, ops.halo, cs), lds_bytes(g + 1, rpt, dim, ops.halo, cs));
+  };
   while (G > 1 && bwd_bytes(G) > lds_limit) --G;
   if (bwd_bytes(G) > lds_limit) {
     *why = "backward state block does not fit in LDS";

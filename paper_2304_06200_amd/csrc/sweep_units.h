@@ -60,7 +60,9 @@ hipError_t run_width(const SweepArgs& a, const SweepShape& sh, hipStream_t st, h
   switch (sh.rows_per_thread) {
     case 1: { HG_BY_WK(1) }
     case 2: { HG_BY_WK(2) }
+    case 3: { HG_BY_WK(3) }
     case 4: { HG_BY_WK(4) }
+    case 6: { HG_BY_WK(6) }
     default: { HG_BY_WK(8) }
   }
 #undef HG_BY_WK

@@ -88,3 +88,23 @@ def test_planner_errors():
     assert e.value.status == _lib.HG_ERR_INVALID_ARG
     m, s = _lib.hg_plan(np.array([], dtype=np.float64), 3, 1e-12, 2.0 ** -53)
     assert m.size == 0
+
+
+def test_planner_exact_at_thresholds():
+    """Norms placed on and one ulp around feasibility thresholds of E_A (found
+    by bisection on the oracle's bound) get the oracle's decision."""
+    from paper_2304_06200_amd import _lib
+    pts = []
+    for (m, s, sig) in [(22, 4, 9), (14, 1, 3), (20, 2, 5), (18, 3, 9)]:
+        lo, hi = 0.0, 64.0
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            if oplan.error_bound(mid, m, s, sig) <= 1e-12:
+                lo = mid
+            else:
+                hi = mid
+        for t in (lo, hi, np.nextafter(lo, 0), np.nextafter(hi, 100), lo * (1 + 1e-13)):
+            pts.append((t, sig))
+    for t, sig in pts:
+        mm, ss = _lib.hg_plan(np.array([t]), sig, 1e-12, 2.0 ** -53)
+        assert (int(mm[0]), int(ss[0])) == oplan.select(float(t), sig, 1e-12), (t, sig)
