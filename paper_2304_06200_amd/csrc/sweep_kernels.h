@@ -77,6 +77,15 @@ __device__ __forceinline__ uint32_t opaque_s(uint32_t x) {
   return x;
 }
 
+// Whether any row of this wavefront's slab r exists (wave-uniform, kept in a
+// scalar register): whole slabs past the dimension are skipped, not masked.
+template <int RPT>
+__device__ __forceinline__ void slab_valid(int d, bool (&sv)[RPT]) {
+  const int w0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) sv[r] = RPT == 1 || w0 + r * (int)blockDim.x < d;
+}
+
 // Deterministic FP64 block sum of NV values; every thread receives the totals.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
@@ -254,7 +263,7 @@ __device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t
 // RPT*W gather addresses in registers (computed once per kernel); multi-vector
 // blocks rebuild each from one per-row base with one add, which keeps the
 // register budget for the extra accumulators.
-template <typename R, int RPT, int W, int V, int WK, bool AUX, bool SRC1>
+template <typename R, int RPT, int NR, int W, int V, int WK, bool AUX, bool SRC1>
 __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, int g0,
                                             const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                             const cx<R> (&bv)[RPT][W],
@@ -264,7 +273,7 @@ __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, i
   using L = Blk<R, RPT, V>;
   using Row = typename L::Row;
   constexpr int NIR = W + (AUX ? (V - 1) * WK : 0);
-  constexpr int NI = RPT * NIR;
+  constexpr int NI = NR * NIR;  // only the first NR rows (a wave's last slab may be empty)
   constexpr int PD = V == 1 ? (sizeof(R) == 4 ? 6 : 3) : (V == 2 && sizeof(R) == 4 ? 3 : 2);
   constexpr int NS = PD + 1;
   const int d = a.d;
@@ -337,19 +346,32 @@ __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, i
 template <typename R, int RPT, int W, int V, int WK, bool AUX>
 __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, int g0,
                                              const uint32_t (&rowb)[RPT],
-                                             const bool (&ok)[RPT], const cx<R> (&bv)[RPT][W],
+                                             const bool (&ok)[RPT], const bool (&sv)[RPT],
+                                             const cx<R> (&bv)[RPT][W],
                                              const cx<R> (&ek)[V][RPT][WK], int m, int s, R sgn,
                                              cx<R> (&acc)[RPT][V]) {
   for (int l = 0; l < s; ++l) {
     block_store<R, RPT, V>(base, a.d, rowb, ok, acc);
     __syncthreads();
+    // a wavefront whose last row slab lies past the dimension runs the
+    // RPT-1 row variant (wave-uniform choice, both variants fully unrolled)
+    const bool full = sv[RPT - 1];
+    constexpr int NRS = RPT > 1 ? RPT - 1 : 1;
     for (int j = 1; j <= m; j += 2) {
-      taylor_term<R, RPT, W, V, WK, AUX, false>(base, a, g0, rowb, ok, bv, ek,
-                                                sgn * inv_int<R>(j), acc);
+      if (full)
+        taylor_term<R, RPT, RPT, W, V, WK, AUX, false>(base, a, g0, rowb, ok, bv, ek,
+                                                       sgn * inv_int<R>(j), acc);
+      else
+        taylor_term<R, RPT, NRS, W, V, WK, AUX, false>(base, a, g0, rowb, ok, bv, ek,
+                                                       sgn * inv_int<R>(j), acc);
       __syncthreads();
       if (j + 1 <= m) {
-        taylor_term<R, RPT, W, V, WK, AUX, true>(base, a, g0, rowb, ok, bv, ek,
-                                                 sgn * inv_int<R>(j + 1), acc);
+        if (full)
+          taylor_term<R, RPT, RPT, W, V, WK, AUX, true>(base, a, g0, rowb, ok, bv, ek,
+                                                        sgn * inv_int<R>(j + 1), acc);
+        else
+          taylor_term<R, RPT, NRS, W, V, WK, AUX, true>(base, a, g0, rowb, ok, bv, ek,
+                                                        sgn * inv_int<R>(j + 1), acc);
         __syncthreads();
       }
     }
@@ -390,7 +412,8 @@ __global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
 
   int row[RPT];
   uint32_t rowb[RPT];
-  bool ok[RPT];
+  bool ok[RPT], sv[RPT];
+  slab_valid<RPT>(d, sv);
   C acc[RPT][1];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
@@ -411,7 +434,7 @@ __global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
     const int s = a.ssch[(size_t)b * a.N + n];
     C bv[RPT][W];
     assemble_B<R, RPT, W>(a, ub, n, row, ok, a.dt / (double)s, bv);
-    taylor_block<R, RPT, W, 1, 1, false>(base, a, 0, rowb, ok, bv, ek, m, s, (R)1, acc);
+    taylor_block<R, RPT, W, 1, 1, false>(base, a, 0, rowb, ok, sv, bv, ek, m, s, (R)1, acc);
     if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
       C p[RPT];
 #pragma unroll
@@ -485,7 +508,8 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
 
   int row[RPT];
   uint32_t rowb1[RPT], rowb2[RPT];
-  bool ok[RPT];
+  bool ok[RPT], sv[RPT];
+  slab_valid<RPT>(d, sv);
   C pl[RPT][2];  // psi and Lambda
   const C* psiN = reinterpret_cast<const C*>(a.psiN);
 
@@ -538,7 +562,7 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
       if (ok[r]) c_cur[opaque(row[r])] = pl[r][1];
 
     // phase 1: psi and Lambda through (T_m(-B))^s together
-    taylor_block<R, RPT, W, 2, 1, false>(base1, a, 0, rowb1, ok, bv, ek1, m, s, (R)-1, pl);
+    taylor_block<R, RPT, W, 2, 1, false>(base1, a, 0, rowb1, ok, sv, bv, ek1, m, s, (R)-1, pl);
     if (a.renorm_every > 0 && n % a.renorm_every == 0) {
       C p[RPT];
 #pragma unroll
@@ -571,7 +595,7 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
 #pragma unroll
         for (int v = 1; v < V2; ++v) yx[r][v] = C{(R)0, (R)0};
       }
-      taylor_block<R, RPT, W, V2, WK, true>(base2, a, g0, rowb2, ok, bv, ek, m, s, (R)1, yx);
+      taylor_block<R, RPT, W, V2, WK, true>(base2, a, g0, rowb2, ok, sv, bv, ek, m, s, (R)1, yx);
       double gv[G];
 #pragma unroll
       for (int v = 0; v < G; ++v) gv[v] = 0.0;

@@ -128,8 +128,9 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
     *why = "union pattern has " + std::to_string(ops.W) + " diagonals (max 13)";
     return false;
   }
-  const int rows = (dim + rpt - 1) / rpt;
-  const int threads = ((rows + 63) / 64) * 64;
+  // one row per thread below 512 rows; above, 8 full waves (2 per SIMD) and
+  // the kernels skip wave slabs past the dimension, which balances the SIMDs
+  const int threads = rpt == 1 ? ((dim + 63) / 64) * 64 : kMaxThreads;
   const size_t cs = c128 ? 16 : 8;
   const size_t fwd = lds_bytes(1, rpt, dim, ops.halo, cs);
   if (fwd > lds_limit) {
