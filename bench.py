@@ -56,6 +56,31 @@ def run_precision(hg, prob, u, psi0, tg, p, dtype, steps, warmup):
             "drift": float(np.max(res.drift))}
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sweep_kernels.h", "sweep_units.h", "sweep_launch.hip"):
+        with open(os.path.join(ROOT, "paper_2304_06200_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per hg_backward launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), or None once the kernel sources differ
+    from the ones the counters were taken on."""
+    path = os.path.join(ROOT, "profiles", "hg_backward_cfg3_c64_hbm_bytes.md")
+    try:
+        txt = open(path).read()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in txt.splitlines()
+                if l.startswith(("traffic_bytes_per_launch:", "kernel_source_sha256_16:")))
+    if vals.get("kernel_source_sha256_16", "").strip() != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"].strip())
+
+
 def cpu_baseline(p_full, n_sample):
     """The FP64 oracle on the first n_sample steps of the same workload (all
     states), scaled to one full evaluation."""
@@ -151,7 +176,8 @@ def main():
                    "sum_mu_per_eval": int(np.mean(main_r["sum_mu"]))},
         "roofline": {"bound": "alu", "kernel": "hg_backward", "achieved": main_r["tflops_backward"],
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": main_r["tflops_backward"] / PEAK_VALU_TFLOPS, "traffic": None},
+                     "frac": main_r["tflops_backward"] / PEAK_VALU_TFLOPS,
+                     "traffic": measured_traffic() if B == 16 else None},
     }
     if "c128" in out:
         c = out["c128"]
