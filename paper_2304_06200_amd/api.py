@@ -124,7 +124,8 @@ def make_desc(n_steps, n_batch, dt, u, n_states, psi0, targets, w_fid, w_pen, ta
 def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.0,
              w_pen: float = 0.0, tau: float = 1e-12, dtype: str = "c128",
              renorm_every: Optional[int] = None, schedule: Optional[np.ndarray] = None,
-             want_grad: bool = True, timing: bool = False, stream=None) -> EvalResult:
+             want_grad: bool = True, timing: bool = False, mode: str = "reconstruct",
+             ckpt_every: int = 0, stream=None) -> EvalResult:
     """Cost and gradient of B amplitude sets.
 
     u        torch float64 device tensor (K, N) or (B, K, N)
@@ -132,6 +133,8 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
     targets  torch complex128 device tensor, same shape as psi0
     dtype    "c128" or "c64" (arithmetic of the Taylor products)
     schedule optional host int array (2, B, N) or (2, N) of frozen (m, s)
+    mode     "reconstruct" (HG inverse propagation) or "checkpoint" (psi stored
+             every ckpt_every steps, segments re-propagated in the backward sweep)
     """
     torch = _torch()
     if u.dim() == 2:
@@ -166,9 +169,10 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
             sched_arr = np.repeat(sched_arr[:, None, :], B, axis=1)
         sched_arr = np.ascontiguousarray(sched_arr.reshape(2, B, N))
         sched_p = sched_arr.ctypes.data_as(C.POINTER(C.c_int32))
+    mcode = {"reconstruct": L.HG_MODE_RECONSTRUCT, "checkpoint": L.HG_MODE_CHECKPOINT}[mode]
     desc = make_desc(N, B, dt, _ptr(u) if K > 0 else None, S, _ptr(psi0), _ptr(targets),
-                     w_fid, w_pen, tau, code, renorm_every, sched_p,
-                     flags=L.HG_FLAG_TIMING if timing else 0)
+                     w_fid, w_pen, tau, code, renorm_every, sched_p, mode=mcode,
+                     ckpt_every=ckpt_every, flags=L.HG_FLAG_TIMING if timing else 0)
     grad = torch.empty((B, K, N), dtype=torch.float64, device=u.device) if want_grad and K > 0 else None
     res = (L.hg_result * B)()
     st = stream if stream is not None else torch.cuda.current_stream(u.device).cuda_stream

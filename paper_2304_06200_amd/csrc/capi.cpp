@@ -252,10 +252,10 @@ hg_status hg_problem_create(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, const hg_c
 
 hg_status hg_problem_destroy(hg_problem* p) {
   if (!p) return HG_OK;
-  hipSetDevice(p->ctx->device);
-  if (p->ops.vals) hipFree(p->ops.vals);
-  if (p->ops.valk) hipFree(p->ops.valk);
-  if (p->ops.omega) hipFree(p->ops.omega);
+  (void)hipSetDevice(p->ctx->device);
+  if (p->ops.vals) (void)hipFree(p->ops.vals);
+  if (p->ops.valk) (void)hipFree(p->ops.valk);
+  if (p->ops.omega) (void)hipFree(p->ops.omega);
   delete p;
   return HG_OK;
 }
@@ -316,10 +316,10 @@ hg_status hg_step_norms(hg_problem* p, const double* u, int32_t n_batch, int32_t
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Workspace {
-  size_t theta, pnorm, sched, psiN, cold, ovl, pen, gradp, drift, res, total;
+  size_t theta, pnorm, sched, psiN, cold, ckpt, segbuf, ovl, pen, gradp, drift, res, total;
 };
 
-static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128) {
+static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128, int ckpt_every) {
   const size_t cs = c128 ? 16 : 8;
   const size_t d = (size_t)p->dim, K = (size_t)p->n_ctrl;
   Workspace w{};
@@ -334,6 +334,10 @@ static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128) {
   w.sched = take((size_t)2 * B * N * 4);
   w.psiN = take((size_t)B * S * d * cs);
   w.cold = take((size_t)B * S * 3 * d * cs);
+  const size_t C = ckpt_every > 0 ? (size_t)std::min(ckpt_every, N) : 0;
+  const size_t nseg = ckpt_every > 0 ? ((size_t)N + ckpt_every - 1) / ckpt_every : 0;
+  w.ckpt = take((size_t)B * S * nseg * d * cs);
+  w.segbuf = take((size_t)B * S * C * d * cs);
   w.ovl = take((size_t)B * S * 16);
   w.pen = take((size_t)B * S * 8);
   w.gradp = take((size_t)B * S * std::max<size_t>(K, 1) * N * 8);
@@ -352,10 +356,10 @@ static hg_status check_desc(const hg_problem* p, const hg_eval_desc* d) {
   if (!std::isfinite(d->w_fid) || !std::isfinite(d->w_pen)) return fail(HG_ERR_NONFINITE, "weights");
   if (!(d->tau > 0.0) || !std::isfinite(d->tau)) return fail(HG_ERR_INVALID_ARG, "tau must be > 0");
   if (d->dtype != HG_C64 && d->dtype != HG_C128) return fail(HG_ERR_INVALID_ARG, "dtype");
-  if (d->mode != HG_MODE_RECONSTRUCT) {
-    if (d->mode != HG_MODE_CHECKPOINT) return fail(HG_ERR_INVALID_ARG, "mode");
-    return fail(HG_ERR_UNSUPPORTED, "checkpoint mode is not built yet");
-  }
+  if (d->mode != HG_MODE_RECONSTRUCT && d->mode != HG_MODE_CHECKPOINT)
+    return fail(HG_ERR_INVALID_ARG, "mode");
+  if (d->mode == HG_MODE_CHECKPOINT && d->ckpt_every < 1)
+    return fail(HG_ERR_INVALID_ARG, "checkpoint mode needs ckpt_every >= 1");
   if (d->renorm_every < 0) return fail(HG_ERR_INVALID_ARG, "renorm_every must be >= 0");
   if ((p->n_ctrl > 0 && !d->u) || !d->psi0 || !d->targets)
     return fail(HG_ERR_INVALID_ARG, "NULL device array");
@@ -366,7 +370,8 @@ hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* d, size_t* 
   hg_status st = check_desc(p, d);
   if (st != HG_OK) return st;
   if (!bytes) return fail(HG_ERR_INVALID_ARG, "bytes is NULL");
-  *bytes = layout(p, d->n_batch, d->n_steps, d->n_states, d->dtype == HG_C128).total;
+  *bytes = layout(p, d->n_batch, d->n_steps, d->n_states, d->dtype == HG_C128,
+                  d->mode == HG_MODE_CHECKPOINT ? d->ckpt_every : 0).total;
   return HG_OK;
 }
 
@@ -388,7 +393,8 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, doub
   sh.n_states = S;
   sh.n_batch = B;
 
-  const Workspace w = layout(p, B, N, S, c128);
+  const int ck = d->mode == HG_MODE_CHECKPOINT ? std::min(d->ckpt_every, N) : 0;
+  const Workspace w = layout(p, B, N, S, c128, ck);
   char* ws = nullptr;
   if (hipMallocAsync((void**)&ws, w.total, hs) != hipSuccess)
     return fail(HG_ERR_OUT_OF_MEMORY, "workspace of " + std::to_string(w.total) + " bytes");
@@ -396,7 +402,7 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, doub
     char* p;
     hipStream_t s;
     ~Free() {
-      if (p) hipFreeAsync(p, s);
+      if (p) (void)hipFreeAsync(p, s);
     }
   } guard{ws, hs};
 
@@ -408,7 +414,7 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, doub
   struct HFree {
     char* p;
     ~HFree() {
-      if (p) hipHostFree(p);
+      if (p) (void)hipHostFree(p);
     }
   } hguard{hbuf};
   double* h_theta = (double*)hbuf;
@@ -471,6 +477,8 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, doub
   bf.targets = d->targets;
   bf.psiN = ws + w.psiN;
   bf.cold = ws + w.cold;
+  bf.ckpt = ck > 0 ? ws + w.ckpt : nullptr;
+  bf.segbuf = ck > 0 ? ws + w.segbuf : nullptr;
   bf.ovl = (double*)(ws + w.ovl);
   bf.pen = (double*)(ws + w.pen);
   bf.gradp = (double*)(ws + w.gradp);
@@ -482,12 +490,12 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, doub
     hipEvent_t* e;
     ~Events() {
       for (int i = 0; i < 3; ++i)
-        if (e[i]) hipEventDestroy(e[i]);
+        if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } evguard{bf.ev};
   if (d->flags & HG_FLAG_TIMING)
     for (int i = 0; i < 3; ++i) HG_HIP(hipEventCreate(&bf.ev[i]));
-  SweepParams sp{d->dt, d->w_fid, d->w_pen, d->renorm_every};
+  SweepParams sp{d->dt, d->w_fid, d->w_pen, d->renorm_every, ck};
   HG_HIP(launch_sweep(p->ops, sh, bf, sp, hs));
   HG_HIP(hipMemcpyAsync(h_res, bf.res, (size_t)B * 8 * 8, hipMemcpyDeviceToHost, hs));
   HG_HIP(hipMemcpyAsync(h_drift, bf.drift, (size_t)B * S * 8, hipMemcpyDeviceToHost, hs));

@@ -83,6 +83,8 @@ struct SweepBuffers {
   const double* targets;           // [B][S][dim] complex128
   void* psiN;                      // [B][S][dim] working precision
   void* cold;                      // [B][S][3][dim] working precision
+  void* ckpt;                      // checkpoint variant: [B][S][ceil(N/C)][dim], else null
+  void* segbuf;                    // checkpoint variant: [B][S][C][dim], else null
   double* ovl;                     // [B][S][2]
   double* pen;                     // [B][S]
   double* gradp;                   // [B][S][K][N]
@@ -94,6 +96,7 @@ struct SweepBuffers {
 struct SweepParams {
   double dt, w_fid, w_pen;
   int renorm_every;
+  int ckpt_every;  // 0: reconstruction; > 0: checkpoint every C steps
 };
 bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_limit,
                      SweepShape* shape, std::string* why);

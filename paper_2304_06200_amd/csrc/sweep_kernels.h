@@ -34,6 +34,7 @@ struct alignas(2 * sizeof(R)) cx {
 
 struct SweepArgs {
   int d, K, N, S, W, halo, G, renorm_every;
+  int ckpt_every;        // > 0: checkpointed-state variant, psi stored every ckpt_every steps
   int off[kMaxDiag];
   int WK[kMaxCtrl];
   int offk[kMaxCtrl][kMaxDiagCtrl];
@@ -47,6 +48,8 @@ struct SweepArgs {
   const double2* tgt;    // [B][S][d]
   void* psiN;            // [B][S][d] (working precision)
   void* cold;            // [B][S][3][d] (working precision)
+  void* ckpt;            // [B][S][ceil(N/C)][d] checkpoints psi_0, psi_C, ... (checkpoint variant)
+  void* segbuf;          // [B][S][C][d] states of the segment being swept back
   double* ovl;           // [B][S][2]
   double* pen;           // [B][S]
   double* gradp;         // [B][S][K][N]
@@ -429,6 +432,13 @@ __global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
   C ek[1][RPT][1];
   double pen = 0.0;
   const double* ub = a.u + (size_t)b * a.K * a.N;
+  const int CK = a.ckpt_every;
+  C* ck = CK > 0 ? reinterpret_cast<C*>(a.ckpt) + ((size_t)b * a.S + h) * (size_t)((a.N + CK - 1) / CK) * d
+                 : nullptr;
+  if (ck)
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+      if (ok[r]) ck[row[r]] = acc[r][0];
   for (int n = 0; n < a.N; ++n) {
     const int m = a.msch[(size_t)b * a.N + n];
     const int s = a.ssch[(size_t)b * a.N + n];
@@ -450,6 +460,10 @@ __global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
           pen += a.omega[row[r]] *
                  ((double)acc[r][0].re * acc[r][0].re + (double)acc[r][0].im * acc[r][0].im);
     }
+    if (ck && (n + 1) % CK == 0 && n + 1 < a.N)
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (ok[r]) ck[(size_t)((n + 1) / CK) * d + row[r]] = acc[r][0];
   }
 
   C* psiN = reinterpret_cast<C*>(a.psiN);
@@ -551,7 +565,49 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
 
   C ek1[2][RPT][1];
   const double* ub = a.u + (size_t)b * K * N;
-  for (int n = N - 1; n >= 0; --n) {
+  // Reconstruction variant: one segment, psi_{n-1} rebuilt by (T_m(-B_n))^s.
+  // Checkpoint variant: segments of CK steps swept back last to first; each is
+  // first re-propagated forward from its stored psi (the same products as the
+  // forward sweep), keeping its states, so only Lambda is propagated backwards.
+  const bool ckpt = a.ckpt_every > 0;
+  const int CK = ckpt ? a.ckpt_every : N;
+  const int nseg = (N + CK - 1) / CK;
+  using LF = Blk<R, RPT, 1>;
+  const uint32_t basef = kRedBytes + a.halo * LF::RB;
+  uint32_t rowbf[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) rowbf[r] = (uint32_t)row[r] * LF::RB;
+  const C* ckb = ckpt ? reinterpret_cast<const C*>(a.ckpt) + ((size_t)b * S + h) * (size_t)nseg * d
+                      : nullptr;
+  C* seg = ckpt ? reinterpret_cast<C*>(a.segbuf) + ((size_t)b * S + h) * (size_t)CK * d : nullptr;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+  const int n0 = ckpt ? sg * CK : 0;
+  const int n1 = ckpt ? (n0 + CK < N ? n0 + CK : N) : N;
+  if (ckpt) {
+    C f[RPT][1];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) f[r][0] = ok[r] ? ckb[(size_t)sg * d + row[r]] : C{(R)0, (R)0};
+    for (int n = n0; n < n1; ++n) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (ok[r]) seg[(size_t)(n - n0) * d + opaque(row[r])] = f[r][0];
+      const int m = a.msch[(size_t)b * N + n];
+      const int s = a.ssch[(size_t)b * N + n];
+      C bv[RPT][W];
+      assemble_B<R, RPT, W>(a, ub, n, row, ok, a.dt / (double)s, bv);
+      C ekf[1][RPT][1];
+      taylor_block<R, RPT, W, 1, 1, false>(basef, a, 0, rowbf, ok, sv, bv, ekf, m, s, (R)1, f);
+      if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
+        C p[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) p[r] = f[r][0];
+        renormalise<R, RPT>(p, red);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) f[r][0] = p[r];
+      }
+    }
+  }
+  for (int n = n1 - 1; n >= n0; --n) {
     const int m = a.msch[(size_t)b * N + n];
     const int s = a.ssch[(size_t)b * N + n];
     const double cs = a.dt / (double)s;
@@ -561,23 +617,39 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
     for (int r = 0; r < RPT; ++r)
       if (ok[r]) c_cur[opaque(row[r])] = pl[r][1];
 
-    // phase 1: psi and Lambda through (T_m(-B))^s together
-    taylor_block<R, RPT, W, 2, 1, false>(base1, a, 0, rowb1, ok, sv, bv, ek1, m, s, (R)-1, pl);
-    if (a.renorm_every > 0 && n % a.renorm_every == 0) {
-      C p[RPT];
+    if (!ckpt) {
+      // phase 1: psi and Lambda through (T_m(-B))^s together
+      taylor_block<R, RPT, W, 2, 1, false>(base1, a, 0, rowb1, ok, sv, bv, ek1, m, s, (R)-1, pl);
+      if (a.renorm_every > 0 && n % a.renorm_every == 0) {
+        C p[RPT];
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) p[r] = pl[r][0];
-      renormalise<R, RPT>(p, red);
+        for (int r = 0; r < RPT; ++r) p[r] = pl[r][0];
+        renormalise<R, RPT>(p, red);
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) pl[r][0] = p[r];
-    }
-#pragma unroll
-    for (int r = 0; r < RPT; ++r)
-      if (ok[r]) {
-        const int i = opaque(row[r]);
-        c_psi[i] = pl[r][0];
-        c_lam[i] = pl[r][1];
+        for (int r = 0; r < RPT; ++r) pl[r][0] = p[r];
       }
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (ok[r]) {
+          const int i = opaque(row[r]);
+          c_psi[i] = pl[r][0];
+          c_lam[i] = pl[r][1];
+        }
+    } else {
+      // phase 1 (checkpoint variant): Lambda alone; psi_{n-1} from the segment
+      C lm[RPT][1];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) lm[r][0] = pl[r][1];
+      C ekf[1][RPT][1];
+      taylor_block<R, RPT, W, 1, 1, false>(basef, a, 0, rowbf, ok, sv, bv, ekf, m, s, (R)-1, lm);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (ok[r]) {
+          const int i = opaque(row[r]);
+          c_psi[i] = seg[(size_t)(n - n0) * d + i];
+          c_lam[i] = lm[r][0];
+        }
+    }
 
     // phase 2: auxiliary actions, G controls per pass
     for (int g0 = 0; g0 < K; g0 += G) {
@@ -625,8 +697,9 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
       }
     }
   }
+  }
 
-  // drift of the rebuilt initial state
+  // drift of the rebuilt initial state (zero by construction in the checkpoint variant)
   double dv[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r)

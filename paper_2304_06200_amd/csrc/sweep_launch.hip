@@ -172,6 +172,7 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
   a.halo = ops.halo;
   a.G = sh.groups;
   a.renorm_every = p.renorm_every;
+  a.ckpt_every = p.ckpt_every;
   for (int e = 0; e < kMaxDiag; ++e) a.off[e] = e < ops.W ? ops.off[e] : 0;
   int wk = 1;
   for (int k = 0; k < kMaxCtrl; ++k) {
@@ -189,6 +190,8 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
   a.tgt = reinterpret_cast<const double2*>(bf.targets);
   a.psiN = bf.psiN;
   a.cold = bf.cold;
+  a.ckpt = bf.ckpt;
+  a.segbuf = bf.segbuf;
   a.ovl = bf.ovl;
   a.pen = bf.pen;
   a.gradp = bf.gradp;
