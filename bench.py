@@ -18,6 +18,9 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# more hardware queues than HIP's default of 4, so the serving loop's concurrent
+# request streams can run side by side (must be set before HIP initialises)
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 METRIC = "cost+gradient evals/s (dim 1600, N=2000, 16 states) c64 vs c128; p99 ms served"
 PEAK_VALU_TFLOPS = 78.6  # unpacked FP32 FMA and FP64 FMA: 256 CU x 64 lanes x 2 flop x 2.4 GHz
@@ -81,6 +84,52 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"].strip())
 
 
+def serving(hg, ctx, dtype, n_req, inflight, budget, load=0.7, seed=4):
+    """cfg4 stream: n_req requests of transmon(3) x cavity(d_c) problems, d_c
+    log-uniform in [8, 700], N in [200, 2000], S in [1, 8].  First all at once
+    (saturated throughput X), then Poisson arrivals at load*X; latency is
+    submit-to-finish per request."""
+    import numpy as np
+    import torch
+    from workloads.configs import serving_request, serving_stream
+    shapes = serving_stream(n_req=n_req, seed=seed)
+    reqs = [serving_request(s["index"], s["d_c"], s["N"], s["S"]) for s in shapes]
+    probs = {}
+    dev = []
+    for p in reqs:
+        if p.dims not in probs:
+            probs[p.dims] = hg.Problem(ctx, p.H0, p.Hk, p.omega)
+        dev.append((probs[p.dims], torch.tensor(p.u, device="cuda"),
+                    torch.tensor(p.psi0, dtype=torch.complex128, device="cuda"),
+                    torch.tensor(p.targets, dtype=torch.complex128, device="cuda")))
+    kw = lambda p: dict(w_fid=p.w_fid, w_pen=p.w_pen, tau=p.tau, dtype=dtype)
+    sv = hg.Server(ctx, hbm_budget_bytes=budget, max_inflight=inflight)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hs = [sv.submit(*dev[i][:1], *dev[i][1:], reqs[i].dt, **kw(reqs[i])) for i in range(n_req)]
+    for h in hs:
+        sv.wait(h)
+    sat = n_req / (time.perf_counter() - t0)
+    log(f"  serving {dtype}: saturated {sat:.2f} req/s")
+    rate = load * sat
+    rng = np.random.default_rng(seed + 1000)
+    gaps = rng.exponential(1.0 / rate, size=n_req)
+    hs = []
+    t0 = time.perf_counter()
+    t_next = t0
+    for i in range(n_req):
+        t_next += gaps[i]
+        delay = t_next - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        hs.append(sv.submit(*dev[i][:1], *dev[i][1:], reqs[i].dt, **kw(reqs[i])))
+    lats = [sv.wait(h)[1] for h in hs]
+    sv.close()
+    st = hg.percentiles(lats)
+    log(f"  serving {dtype}: at {rate:.2f} req/s p50 {st['p50_ms']:.0f} ms p99 {st['p99_ms']:.0f} ms")
+    return {"saturated_req_per_s": sat, "offered_req_per_s": rate, **st}
+
+
 def cpu_baseline(p_full, n_sample):
     """The FP64 oracle on the first n_sample steps of the same workload (all
     states), scaled to one full evaluation."""
@@ -112,6 +161,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c128", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-inflight", type=int, default=16)
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for the "
                          "FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -187,6 +239,17 @@ def main():
         line["c64_over_c128"] = main_r["evals_per_s"] / c["evals_per_s"]
     line["kernel_ms"] = {d: {"forward": out[d]["ms_forward"], "backward": out[d]["ms_backward"]}
                          for d in out}
+    if not args.no_serving:
+        log(f"[bench] serving stream: {args.serve_requests} requests, {args.serve_inflight} slots")
+        budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)
+        line["served"] = {
+            "workload": "cfg4: transmon(3) x cavity(d_c log-uniform 8..700), N 200..2000, S 1..8, "
+                        "dt=1 ns, tau=1e-10, Poisson arrivals at 0.7 x saturated rate",
+            "requests": args.serve_requests, "slots": args.serve_inflight, "hbm_budget_bytes": budget}
+        for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
+            line["served"][dtype] = serving(hg, ctx, dtype, args.serve_requests,
+                                            args.serve_inflight, budget)
+        line["served"]["p99_ms"] = line["served"]["c64"]["p99_ms"]
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {args.cpu_sample} steps")
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_sample)

@@ -171,6 +171,39 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* desc, hg_result* results,
  * shape (workspace only; caller buffers excluded).  Used for admission. */
 hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* desc, size_t* bytes);
 
+/* ---------------------------------------------------------------- serving ----
+ * A server admits cost+gradient requests (any problem, any shape) onto the
+ * context's GPU as they arrive: a request starts when one of max_inflight
+ * worker slots is free and its device footprint (hg_eval_footprint plus its
+ * own u, psi0, targets and grad buffers) fits in hbm_budget_bytes next to the
+ * running requests; admission is first come, first served.  Each slot runs on
+ * its own HIP stream, so kernels of concurrent requests overlap on the
+ * device.  A request's results do not depend on what runs beside it.
+ * The desc's device buffers, `results` (host [n_batch]) and `grad` must stay
+ * valid until hg_server_wait returns for the request; a frozen schedule is
+ * copied at submit.  All server calls are thread-safe. */
+typedef struct hg_server hg_server;
+
+hg_status hg_server_create(hg_ctx* ctx, size_t hbm_budget_bytes, int32_t max_inflight,
+                           hg_server** out);
+/* Queue a request.  Errors at submit: INVALID_ARG (and the other hg_eval
+ * argument checks), OUT_OF_MEMORY (footprint larger than the whole budget),
+ * BUSY (queue full or server shutting down).  Writes the request id. */
+hg_status hg_server_submit(hg_server* sv, hg_problem* p, const hg_eval_desc* desc,
+                           hg_result* results, double* grad, uint64_t* req_id);
+/* done = 1 once the request finished (successfully or not). */
+hg_status hg_server_poll(hg_server* sv, uint64_t req_id, int32_t* done);
+/* Block until the request finished; returns its hg_eval status (CANCELLED if it
+ * was cancelled) and, if non-NULL, the submit-to-finish and submit-to-start
+ * times in ms.  The id is released afterwards. */
+hg_status hg_server_wait(hg_server* sv, uint64_t req_id, double* latency_ms, double* queued_ms);
+/* Cancel a request that has not started (BUSY once it has). */
+hg_status hg_server_cancel(hg_server* sv, uint64_t req_id);
+/* Device bytes admitted right now, queued and running request counts. */
+hg_status hg_server_info(hg_server* sv, size_t* bytes_in_use, int32_t* queued, int32_t* running);
+/* Run every queued request to completion, then stop the workers and free. */
+hg_status hg_server_destroy(hg_server* sv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,7 +70,7 @@ class hg_result(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          f"`python -m paper_2304_06200_amd.build` (hipcc, gfx950)")
+                          f"`python paper_2304_06200_amd/build.py` (hipcc, gfx950)")
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
     sig = {
@@ -91,6 +91,15 @@ def _load():
         "hg_step_norms": (C.c_int, [P, P, C.c_int32, C.c_int32, C.c_double, P, P]),
         "hg_eval": (C.c_int, [P, C.POINTER(hg_eval_desc), C.POINTER(hg_result), P, P]),
         "hg_eval_footprint": (C.c_int, [P, C.POINTER(hg_eval_desc), C.POINTER(C.c_size_t)]),
+        "hg_server_create": (C.c_int, [P, C.c_size_t, C.c_int32, C.POINTER(P)]),
+        "hg_server_submit": (C.c_int, [P, P, C.POINTER(hg_eval_desc), C.POINTER(hg_result), P,
+                                       C.POINTER(C.c_uint64)]),
+        "hg_server_poll": (C.c_int, [P, C.c_uint64, C.POINTER(C.c_int32)]),
+        "hg_server_wait": (C.c_int, [P, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "hg_server_cancel": (C.c_int, [P, C.c_uint64]),
+        "hg_server_info": (C.c_int, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32)]),
+        "hg_server_destroy": (C.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -102,7 +111,9 @@ def _load():
 _lib = _load()
 EXPORTED = ("hg_create", "hg_destroy", "hg_status_string", "hg_last_error", "hg_version",
             "hg_problem_create", "hg_problem_destroy", "hg_problem_info", "hg_plan",
-            "hg_error_bound", "hg_step_norms", "hg_eval", "hg_eval_footprint")
+            "hg_error_bound", "hg_step_norms", "hg_eval", "hg_eval_footprint",
+            "hg_server_create", "hg_server_submit", "hg_server_poll", "hg_server_wait",
+            "hg_server_cancel", "hg_server_info", "hg_server_destroy")
 
 
 def _check(status: int, func: str):
@@ -183,3 +194,44 @@ def hg_eval_footprint(p: int, desc: hg_eval_desc) -> int:
     out = C.c_size_t()
     _check(_lib.hg_eval_footprint(p, C.byref(desc), C.byref(out)), "hg_eval_footprint")
     return int(out.value)
+
+
+def hg_server_create(ctx: int, hbm_budget_bytes: int, max_inflight: int) -> int:
+    out = C.c_void_p()
+    _check(_lib.hg_server_create(ctx, hbm_budget_bytes, max_inflight, C.byref(out)),
+           "hg_server_create")
+    return out.value
+
+
+def hg_server_submit(sv: int, p: int, desc: hg_eval_desc, results, grad_ptr) -> int:
+    rid = C.c_uint64()
+    _check(_lib.hg_server_submit(sv, p, C.byref(desc), results, grad_ptr, C.byref(rid)),
+           "hg_server_submit")
+    return int(rid.value)
+
+
+def hg_server_poll(sv: int, req_id: int) -> bool:
+    done = C.c_int32()
+    _check(_lib.hg_server_poll(sv, req_id, C.byref(done)), "hg_server_poll")
+    return bool(done.value)
+
+
+def hg_server_wait(sv: int, req_id: int):
+    """Returns (status, latency_ms, queued_ms); the status is not raised."""
+    lat, q = C.c_double(), C.c_double()
+    st = _lib.hg_server_wait(sv, req_id, C.byref(lat), C.byref(q))
+    return int(st), float(lat.value), float(q.value)
+
+
+def hg_server_cancel(sv: int, req_id: int) -> None:
+    _check(_lib.hg_server_cancel(sv, req_id), "hg_server_cancel")
+
+
+def hg_server_info(sv: int):
+    b, q, r = C.c_size_t(), C.c_int32(), C.c_int32()
+    _check(_lib.hg_server_info(sv, C.byref(b), C.byref(q), C.byref(r)), "hg_server_info")
+    return int(b.value), int(q.value), int(r.value)
+
+
+def hg_server_destroy(sv: int) -> None:
+    _check(_lib.hg_server_destroy(sv), "hg_server_destroy")

@@ -1,7 +1,9 @@
 """Build libhgrape.so (HIP for gfx950) in-tree.
 
-    python -m paper_2304_06200_amd.build            # all sources, parallel
-    python -m paper_2304_06200_amd.build --jobs 4
+    python paper_2304_06200_amd/build.py            # all sources, parallel
+    python paper_2304_06200_amd/build.py --jobs 4
+
+(run it by path: importing the package loads the library being rebuilt)
 
 Every .hip/.cpp translation unit under csrc/ is compiled with hipcc for
 --offload-arch=gfx950 (packed FP32 instructions disabled), except plan.cpp,
