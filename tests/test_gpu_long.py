@@ -1,0 +1,74 @@
+"""Long sweeps: transmon(8) x cavity, N = 5000 steps of dt = 0.2 ns, 4 states,
+forbidden-level penalty on.  Inverse reconstruction against the
+checkpointed-state variant (a state stored every 100 steps), complex64 and
+complex128, with the reconstruction drift and the device footprint of both
+variants reported.
+
+The full-size problem (cavity 1024, d = 8192) exceeds what one workgroup holds
+and is rejected with HG_ERR_UNSUPPORTED (tested below).  The sweep runs at
+cavity 256 (d = 2048), the largest size whose complex128 backward block fits in
+LDS, against the Taylor-discretised oracle evaluated offline
+(tests/golden/make_golden.py cfg5:d_c=256 --discrete, states stored, no
+reconstruction) with the oracle planner's schedule."""
+import numpy as np
+import pytest
+
+from gpu_common import assert_parity, golden, log, make_problem, run
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = "cfg5_t8c256_discrete"
+
+
+def test_full_size_rejected():
+    import paper_2304_06200_amd as hg
+    from paper_2304_06200_amd import _lib as L
+    p = make_config("cfg5", N=3)
+    log(f"[case] cfg5 full size d={p.dim}: expect UNSUPPORTED")
+    prob = make_problem(p)
+    for dt in ("c64", "c128"):
+        with pytest.raises(hg._lib.HGError) as e:
+            run(p, dt, prob=prob)
+        assert e.value.status == L.HG_ERR_UNSUPPORTED, str(e.value)
+        log(f"  {dt}: {e.value}")
+
+
+@pytest.fixture(scope="module")
+def long_case():
+    ref = golden(GOLDEN)
+    if ref is None:
+        pytest.skip(f"tests/golden/{GOLDEN}_oracle.npz not generated")
+    p = make_config("cfg5", d_c=256)
+    assert p.dim == int(ref["dim"]) and p.n_steps == int(ref["n_steps"])
+    return p, make_problem(p), ref
+
+
+def _footprint(prob, p, dtype, mode, C=0):
+    from paper_2304_06200_amd import _lib as L
+    from paper_2304_06200_amd.api import make_desc
+    desc = make_desc(p.n_steps, 1, p.dt, 1, p.n_states, 1, 1, p.w_fid, p.w_pen, p.tau,
+                     L.HG_C128 if dtype == "c128" else L.HG_C64, 1, None, mode=mode,
+                     ckpt_every=C)
+    return L.hg_eval_footprint(prob.handle, desc)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_long_reconstruct_vs_checkpoint(long_case, dtype):
+    from paper_2304_06200_amd import _lib as L
+    p, prob, ref = long_case
+    sched = np.asarray(ref["schedule"], dtype=np.int64)
+    sum_mu = int(np.sum(sched[0] * sched[1]))
+    log(f"[case] cfg5 d_c=256 d={p.dim} N={p.n_steps} S={p.n_states} {dtype}, sum_mu {sum_mu}")
+    a = run(p, dtype, prob=prob)
+    log(f"  reconstruct: drift {a.drift[0]:.3e}, footprint "
+        f"{_footprint(prob, p, dtype, L.HG_MODE_RECONSTRUCT) / 2**20:.1f} MiB")
+    b = run(p, dtype, prob=prob, mode="checkpoint", ckpt_every=100)
+    log(f"  checkpoint C=100: drift {b.drift[0]:.3e}, footprint "
+        f"{_footprint(prob, p, dtype, L.HG_MODE_CHECKPOINT, 100) / 2**20:.1f} MiB")
+    assert a.sum_mu[0] == sum_mu and b.sum_mu[0] == sum_mu
+    assert_parity(a, ref, dtype, label="cfg5r-reconstruct")
+    assert_parity(b, ref, dtype, label="cfg5r-ckpt100")
+    assert b.drift[0] == 0.0
+    if dtype == "c128":
+        assert a.drift[0] < 1e-9
