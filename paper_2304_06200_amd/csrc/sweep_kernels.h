@@ -238,12 +238,25 @@ __device__ __forceinline__ void lds_st(uint32_t off, const T& v) {
 }
 
 // Write the V accumulators of this thread's rows into buffer 0 of the block.
+// With a shared tail slab (see taylor_block) the last row carries only vector
+// tv of this wave (none if tv < 0), written on its own.
 template <typename R, int RPT, int V>
 __device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t (&rowb)[RPT],
-                                            const bool (&ok)[RPT], const cx<R> (&acc)[RPT][V]) {
+                                            const bool (&ok)[RPT], bool split, int tv,
+                                            const cx<R> (&acc)[RPT][V]) {
   using L = Blk<R, RPT, V>;
 #pragma unroll
-  for (int r = 0; r < RPT; ++r)
+  for (int r = 0; r < RPT; ++r) {
+    if (split && r == RPT - 1) {
+      if (tv >= 0 && ok[r]) {
+        cx<R> x = acc[r][0];
+#pragma unroll
+        for (int v = 1; v < V; ++v)
+          if (tv == v) x = acc[r][v];
+        lds_st(base + rowb[r] + (uint32_t)(tv / L::VP) * L::ps(d) + (uint32_t)(tv % L::VP) * L::CS, x);
+      }
+      continue;
+    }
     if (ok[r])
 #pragma unroll
       for (int p = 0; p < L::NP; ++p) {
@@ -252,6 +265,7 @@ __device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t
         for (int q = 0; q < L::VP; ++q) w.v[q] = (p * L::VP + q < V) ? acc[r][p * L::VP + q] : cx<R>{(R)0, (R)0};
         lds_st(base + rowb[r] + p * L::ps(d), w);
       }
+  }
 }
 
 // One Taylor term for the V vectors of this thread's rows, reading buffer
@@ -338,6 +352,70 @@ __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, i
   }
 }
 
+// The shared tail slab's share of one Taylor term: vector VT of the last row
+// (RPT-1) only, with the same products as taylor_term for that vector.
+template <typename R, int RPT, int W, int V, int WK, bool AUX, bool SRC1, int VT>
+__device__ __forceinline__ void tail_piece(uint32_t base, const SweepArgs& a, int g0,
+                                           const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
+                                           const cx<R> (&bv)[RPT][W],
+                                           const cx<R> (&ek)[V][RPT][WK], R inv,
+                                           cx<R> (&acc)[RPT][V]) {
+  using C = cx<R>;
+  using L = Blk<R, RPT, V>;
+  constexpr int r = RPT - 1;
+  const int d = a.d;
+  const uint32_t SRC = SRC1 ? L::bs(d) : 0, DST = SRC1 ? 0 : L::bs(d);
+  const uint32_t vo = (uint32_t)(VT / L::VP) * L::ps(d) + (uint32_t)(VT % L::VP) * L::CS;
+  const uint32_t rb = (uint32_t)opaque((int)rowb[r]);
+  C x[W];
+#pragma unroll
+  for (int q = 0; q < W; ++q)
+    x[q] = lds_ld<C>(rb + opaque_s((uint32_t)(a.off[q] * L::RB) + base + SRC) + vo);
+  C y[(AUX && VT > 0) ? WK : 1];
+  if constexpr (AUX && VT > 0) {
+    const int kk = g0 + VT - 1 < a.K ? g0 + VT - 1 : 0;
+#pragma unroll
+    for (int q = 0; q < WK; ++q)
+      y[q] = lds_ld<C>(rb + opaque_s((uint32_t)(a.offk[kk][q] * L::RB) + base + SRC));
+  }
+  C t{(R)0, (R)0};
+#pragma unroll
+  for (int q = 0; q < W; ++q) cmac(t, bv[r][q], x[q]);
+  if constexpr (AUX && VT > 0) {
+#pragma unroll
+    for (int q = 0; q < WK; ++q) cmac(t, ek[VT][r][q], y[q]);
+  }
+  t.re *= inv;
+  t.im *= inv;
+  acc[r][VT].re += t.re;
+  acc[r][VT].im += t.im;
+  if (ok[r]) lds_st(rb + opaque_s(base + DST) + vo, t);
+}
+
+template <typename R, int RPT, int W, int V, int WK, bool AUX, bool SRC1>
+__device__ __forceinline__ void tail_share(int tv, uint32_t base, const SweepArgs& a, int g0,
+                                           const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
+                                           const cx<R> (&bv)[RPT][W],
+                                           const cx<R> (&ek)[V][RPT][WK], R inv,
+                                           cx<R> (&acc)[RPT][V]) {
+  switch (tv) {
+    case 0:
+      tail_piece<R, RPT, W, V, WK, AUX, SRC1, 0>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      break;
+    case 1:
+      if constexpr (V > 1) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 1>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      break;
+    case 2:
+      if constexpr (V > 2) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 2>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      break;
+    case 3:
+      if constexpr (V > 3) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 3>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      break;
+    default:
+      break;
+  }
+}
+
 // One application of (T_m(sgn*B))^s to the V vectors held in `acc`:
 //   t_0 = acc, t_j = (sgn B / j) t_{j-1}, acc += t_j   (Sec. III.B, eq. eBmpsi)
 // repeated s times (scaling and squaring, eq. scaling squaring).  With AUX,
@@ -350,31 +428,36 @@ template <typename R, int RPT, int W, int V, int WK, bool AUX>
 __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, int g0,
                                              const uint32_t (&rowb)[RPT],
                                              const bool (&ok)[RPT], const bool (&sv)[RPT],
+                                             bool split, int tv,
                                              const cx<R> (&bv)[RPT][W],
                                              const cx<R> (&ek)[V][RPT][WK], int m, int s, R sgn,
                                              cx<R> (&acc)[RPT][V]) {
+  // A wavefront whose last row slab lies past the dimension runs the RPT-1 row
+  // variant (wave-uniform choice, both variants fully unrolled).  With a shared
+  // tail slab (`split`: the last plane holds a single slab), every wavefront
+  // runs RPT-1 rows and the tail's vectors are spread over the wavefronts of
+  // different SIMDs: vector tv by this one (V == 1: the whole tail if tv == 0).
+  const bool full = split ? (V == 1 && tv == 0) : sv[RPT - 1];
+  const bool share = sizeof(R) == 4 && split && V > 1 && tv >= 0;
+  constexpr int NRS = RPT > 1 ? RPT - 1 : 1;
   for (int l = 0; l < s; ++l) {
-    block_store<R, RPT, V>(base, a.d, rowb, ok, acc);
+    block_store<R, RPT, V>(base, a.d, rowb, ok, split, tv, acc);
     __syncthreads();
-    // a wavefront whose last row slab lies past the dimension runs the
-    // RPT-1 row variant (wave-uniform choice, both variants fully unrolled)
-    const bool full = sv[RPT - 1];
-    constexpr int NRS = RPT > 1 ? RPT - 1 : 1;
     for (int j = 1; j <= m; j += 2) {
+      const R i1 = sgn * inv_int<R>(j);
       if (full)
-        taylor_term<R, RPT, RPT, W, V, WK, AUX, false>(base, a, g0, rowb, ok, bv, ek,
-                                                       sgn * inv_int<R>(j), acc);
+        taylor_term<R, RPT, RPT, W, V, WK, AUX, false>(base, a, g0, rowb, ok, bv, ek, i1, acc);
       else
-        taylor_term<R, RPT, NRS, W, V, WK, AUX, false>(base, a, g0, rowb, ok, bv, ek,
-                                                       sgn * inv_int<R>(j), acc);
+        taylor_term<R, RPT, NRS, W, V, WK, AUX, false>(base, a, g0, rowb, ok, bv, ek, i1, acc);
+      if (share) tail_share<R, RPT, W, V, WK, AUX, false>(tv, base, a, g0, rowb, ok, bv, ek, i1, acc);
       __syncthreads();
       if (j + 1 <= m) {
+        const R i2 = sgn * inv_int<R>(j + 1);
         if (full)
-          taylor_term<R, RPT, RPT, W, V, WK, AUX, true>(base, a, g0, rowb, ok, bv, ek,
-                                                        sgn * inv_int<R>(j + 1), acc);
+          taylor_term<R, RPT, RPT, W, V, WK, AUX, true>(base, a, g0, rowb, ok, bv, ek, i2, acc);
         else
-          taylor_term<R, RPT, NRS, W, V, WK, AUX, true>(base, a, g0, rowb, ok, bv, ek,
-                                                        sgn * inv_int<R>(j + 1), acc);
+          taylor_term<R, RPT, NRS, W, V, WK, AUX, true>(base, a, g0, rowb, ok, bv, ek, i2, acc);
+        if (share) tail_share<R, RPT, W, V, WK, AUX, true>(tv, base, a, g0, rowb, ok, bv, ek, i2, acc);
         __syncthreads();
       }
     }
@@ -444,7 +527,7 @@ __global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
     const int s = a.ssch[(size_t)b * a.N + n];
     C bv[RPT][W];
     assemble_B<R, RPT, W>(a, ub, n, row, ok, a.dt / (double)s, bv);
-    taylor_block<R, RPT, W, 1, 1, false>(base, a, 0, rowb, ok, sv, bv, ek, m, s, (R)1, acc);
+    taylor_block<R, RPT, W, 1, 1, false>(base, a, 0, rowb, ok, sv, false, -1, bv, ek, m, s, (R)1, acc);
     if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
       C p[RPT];
 #pragma unroll
@@ -520,9 +603,20 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
   C* const c_lam = cold + d;      // propagated co-state
   C* const c_cur = cold + 2 * d;  // Lambda_n (for the overlaps)
 
+  // Shared tail slab: when the last plane of rows holds one slab (at most 64
+  // rows), wavefronts 0..3 (one per SIMD) all map their last row to it and
+  // own one vector each there: psi -> 0, Lambda -> 1 in phase 1, Y -> 0 and
+  // X_v -> v in phase 2.  A thread's copy of a tail vector it does not own
+  // stays zero, so sums over rows need no extra test; stores are guarded.
+  // (complex64 only: the complex128 kernels have no registers to spare for it)
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tail0 = (RPT - 1) * NT;
+  const bool split = sizeof(R) == 4 && RPT > 1 && d > tail0 && d - tail0 <= 64;
+  const bool tailw = split && wv < 4;
+
   int row[RPT];
   uint32_t rowb1[RPT], rowb2[RPT];
-  bool ok[RPT], sv[RPT];
+  bool ok[RPT], sv[RPT], own_psi[RPT], own_lam[RPT];
   slab_valid<RPT>(d, sv);
   C pl[RPT][2];  // psi and Lambda
   const C* psiN = reinterpret_cast<const C*>(a.psiN);
@@ -549,19 +643,28 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
   const double fr = -a.w_fid * gre / S, fi = -a.w_fid * gim / S;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int i = tid + r * NT;
+    const bool shared = split && r == RPT - 1;
+    const int i = (shared && tailw) ? tail0 + (tid & 63) : tid + r * NT;
     ok[r] = i < d;
+    own_psi[r] = ok[r] && (!shared || wv == 0);
+    own_lam[r] = ok[r] && (!shared || wv == 1);
     row[r] = ok[r] ? i : d - 1;
     rowb1[r] = (uint32_t)row[r] * L1::RB;
     rowb2[r] = (uint32_t)row[r] * L2::RB;
     const C p = psiN[col0 + row[r]];
     const double2 t = a.tgt[col0 + row[r]];
     const double w = a.omega ? a.omega[row[r]] : 0.0;
-    pl[r][0] = ok[r] ? p : C{(R)0, (R)0};
-    pl[r][1].re = ok[r] ? (R)(fr * t.x - fi * t.y + cpen * w * (double)p.re) : (R)0;
-    pl[r][1].im = ok[r] ? (R)(fr * t.y + fi * t.x + cpen * w * (double)p.im) : (R)0;
+    pl[r][0] = own_psi[r] ? p : C{(R)0, (R)0};
+    pl[r][1].re = own_lam[r] ? (R)(fr * t.x - fi * t.y + cpen * w * (double)p.re) : (R)0;
+    pl[r][1].im = own_lam[r] ? (R)(fr * t.y + fi * t.x + cpen * w * (double)p.im) : (R)0;
   }
   __syncthreads();
+  // tail vector of this wavefront in the phase-1 block, the phase-2 block and
+  // the single-vector blocks of psi and of Lambda
+  const int tv1 = tailw && wv < 2 ? wv : -1;
+  const int tv2 = tailw && wv < V2 ? wv : -1;
+  const int tvp = tailw && wv == 0 ? 0 : -1;
+  const int tvl = tailw && wv == 1 ? 0 : -1;
 
   C ek1[2][RPT][1];
   const double* ub = a.u + (size_t)b * K * N;
@@ -586,17 +689,18 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
   if (ckpt) {
     C f[RPT][1];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) f[r][0] = ok[r] ? ckb[(size_t)sg * d + row[r]] : C{(R)0, (R)0};
+    for (int r = 0; r < RPT; ++r) f[r][0] = own_psi[r] ? ckb[(size_t)sg * d + row[r]] : C{(R)0, (R)0};
     for (int n = n0; n < n1; ++n) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
-        if (ok[r]) seg[(size_t)(n - n0) * d + opaque(row[r])] = f[r][0];
+        if (own_psi[r]) seg[(size_t)(n - n0) * d + opaque(row[r])] = f[r][0];
       const int m = a.msch[(size_t)b * N + n];
       const int s = a.ssch[(size_t)b * N + n];
       C bv[RPT][W];
       assemble_B<R, RPT, W>(a, ub, n, row, ok, a.dt / (double)s, bv);
       C ekf[1][RPT][1];
-      taylor_block<R, RPT, W, 1, 1, false>(basef, a, 0, rowbf, ok, sv, bv, ekf, m, s, (R)1, f);
+      taylor_block<R, RPT, W, 1, 1, false>(basef, a, 0, rowbf, ok, sv, split, tvp, bv, ekf, m, s,
+                                           (R)1, f);
       if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
         C p[RPT];
 #pragma unroll
@@ -615,11 +719,12 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
     assemble_B<R, RPT, W>(a, ub, n, row, ok, cs, bv);
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
-      if (ok[r]) c_cur[opaque(row[r])] = pl[r][1];
+      if (own_lam[r]) c_cur[opaque(row[r])] = pl[r][1];
 
     if (!ckpt) {
       // phase 1: psi and Lambda through (T_m(-B))^s together
-      taylor_block<R, RPT, W, 2, 1, false>(base1, a, 0, rowb1, ok, sv, bv, ek1, m, s, (R)-1, pl);
+      taylor_block<R, RPT, W, 2, 1, false>(base1, a, 0, rowb1, ok, sv, split, tv1, bv, ek1, m, s,
+                                           (R)-1, pl);
       if (a.renorm_every > 0 && n % a.renorm_every == 0) {
         C p[RPT];
 #pragma unroll
@@ -629,26 +734,25 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
         for (int r = 0; r < RPT; ++r) pl[r][0] = p[r];
       }
 #pragma unroll
-      for (int r = 0; r < RPT; ++r)
-        if (ok[r]) {
-          const int i = opaque(row[r]);
-          c_psi[i] = pl[r][0];
-          c_lam[i] = pl[r][1];
-        }
+      for (int r = 0; r < RPT; ++r) {
+        const int i = opaque(row[r]);
+        if (own_psi[r]) c_psi[i] = pl[r][0];
+        if (own_lam[r]) c_lam[i] = pl[r][1];
+      }
     } else {
       // phase 1 (checkpoint variant): Lambda alone; psi_{n-1} from the segment
       C lm[RPT][1];
 #pragma unroll
       for (int r = 0; r < RPT; ++r) lm[r][0] = pl[r][1];
       C ekf[1][RPT][1];
-      taylor_block<R, RPT, W, 1, 1, false>(basef, a, 0, rowbf, ok, sv, bv, ekf, m, s, (R)-1, lm);
+      taylor_block<R, RPT, W, 1, 1, false>(basef, a, 0, rowbf, ok, sv, split, tvl, bv, ekf, m, s,
+                                           (R)-1, lm);
 #pragma unroll
-      for (int r = 0; r < RPT; ++r)
-        if (ok[r]) {
-          const int i = opaque(row[r]);
-          c_psi[i] = seg[(size_t)(n - n0) * d + i];
-          c_lam[i] = lm[r][0];
-        }
+      for (int r = 0; r < RPT; ++r) {
+        const int i = opaque(row[r]);
+        if (own_psi[r]) c_psi[i] = seg[(size_t)(n - n0) * d + i];
+        if (own_lam[r]) c_lam[i] = lm[r][0];
+      }
     }
 
     // phase 2: auxiliary actions, G controls per pass
@@ -663,11 +767,13 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
       C yx[RPT][V2];
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        yx[r][0] = ok[r] ? c_psi[opaque(row[r])] : C{(R)0, (R)0};
+        // Y starts from psi_{n-1}: on the shared tail only its owner (wave 0)
+        yx[r][0] = own_psi[r] ? c_psi[opaque(row[r])] : C{(R)0, (R)0};
 #pragma unroll
         for (int v = 1; v < V2; ++v) yx[r][v] = C{(R)0, (R)0};
       }
-      taylor_block<R, RPT, W, V2, WK, true>(base2, a, g0, rowb2, ok, sv, bv, ek, m, s, (R)1, yx);
+      taylor_block<R, RPT, W, V2, WK, true>(base2, a, g0, rowb2, ok, sv, split, tv2, bv, ek, m, s,
+                                            (R)1, yx);
       double gv[G];
 #pragma unroll
       for (int v = 0; v < G; ++v) gv[v] = 0.0;
@@ -688,12 +794,13 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int i = opaque(row[r]);
-      pl[r][0] = ok[r] ? c_psi[i] : C{(R)0, (R)0};
-      pl[r][1] = ok[r] ? c_lam[i] : C{(R)0, (R)0};
-      if (n >= 1 && a.omega && ok[r]) {
+      const C ps = ok[r] ? c_psi[i] : C{(R)0, (R)0};
+      pl[r][0] = own_psi[r] ? ps : C{(R)0, (R)0};
+      pl[r][1] = own_lam[r] ? c_lam[i] : C{(R)0, (R)0};
+      if (n >= 1 && a.omega && own_lam[r]) {
         const double w = cpen * a.omega[i];
-        pl[r][1].re = (R)((double)pl[r][1].re + w * (double)pl[r][0].re);
-        pl[r][1].im = (R)((double)pl[r][1].im + w * (double)pl[r][0].im);
+        pl[r][1].re = (R)((double)pl[r][1].re + w * (double)ps.re);
+        pl[r][1].im = (R)((double)pl[r][1].im + w * (double)ps.im);
       }
     }
   }
@@ -703,7 +810,7 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
   double dv[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r)
-    if (ok[r]) {
+    if (own_psi[r]) {
       const double2 p0 = a.psi0[col0 + row[r]];
       const double dr = (double)pl[r][0].re - p0.x, di = (double)pl[r][0].im - p0.y;
       dv[0] += dr * dr + di * di;
