@@ -181,11 +181,23 @@ __constant__ double kInvD[kMMax + 1] = {
     1. / 54,   1. / 55,   1. / 56, 1. / 57, 1. / 58, 1. / 59, 1. / 60};
 
 template <typename R>
-__device__ __forceinline__ R inv_int(int j);
+__device__ __forceinline__ R inv_const(int j);
 template <>
-__device__ __forceinline__ float inv_int<float>(int j) { return kInvF[j]; }
+__device__ __forceinline__ float inv_const<float>(int j) { return kInvF[j]; }
 template <>
-__device__ __forceinline__ double inv_int<double>(int j) { return kInvD[j]; }
+__device__ __forceinline__ double inv_const<double>(int j) { return kInvD[j]; }
+
+// The kernels copy the table into LDS (after the reduction scratch) at start
+// and read 1/j from there inside the term loop: a scalar-memory load in flight
+// would share the LDS wait counter and force every pipelined gather of the term
+// to wait for it (scalar loads return out of order).
+constexpr int kInvOff = 512;
+static_assert(kInvOff + (kMMax + 1) * 8 <= 1024, "1/j table must fit the LDS scratch");
+template <typename R>
+__device__ __forceinline__ void inv_table_to_lds(unsigned char* smem) {
+  if ((int)threadIdx.x <= kMMax)
+    reinterpret_cast<R*>(smem + kInvOff)[threadIdx.x] = inv_const<R>((int)threadIdx.x);
+}
 
 // ---------------------------------------------------------- LDS state block --
 // A double-buffered block of V vectors is stored as planes of 16-byte rows:
@@ -240,11 +252,11 @@ __device__ __forceinline__ void lds_st(uint32_t off, const T& v) {
 // Write the V accumulators of this thread's rows into buffer 0 of the block.
 // With a shared tail slab (see taylor_block) the last row carries only vector
 // tv of this wave (none if tv < 0), written on its own.
-template <typename R, int RPT, int V>
+template <typename R, int RPT, int V, int LR = RPT>
 __device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t (&rowb)[RPT],
                                             const bool (&ok)[RPT], bool split, int tv,
                                             const cx<R> (&acc)[RPT][V]) {
-  using L = Blk<R, RPT, V>;
+  using L = Blk<R, LR, V>;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     if (split && r == RPT - 1) {
@@ -280,14 +292,14 @@ __device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t
 // RPT*W gather addresses in registers (computed once per kernel); multi-vector
 // blocks rebuild each from one per-row base with one add, which keeps the
 // register budget for the extra accumulators.
-template <typename R, int RPT, int NR, int W, int V, int WK, bool AUX, bool SRC1>
+template <typename R, int RPT, int NR, int W, int V, int WK, bool AUX, bool SRC1, int LR = RPT>
 __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, int g0,
                                             const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                             const cx<R> (&bv)[RPT][W],
                                             const cx<R> (&ek)[V][RPT][WK], R inv,
                                             cx<R> (&acc)[RPT][V]) {
   using C = cx<R>;
-  using L = Blk<R, RPT, V>;
+  using L = Blk<R, LR, V>;
   using Row = typename L::Row;
   constexpr int NIR = W + (AUX ? (V - 1) * WK : 0);
   constexpr int NI = NR * NIR;  // only the first NR rows (a wave's last slab may be empty)
@@ -354,14 +366,14 @@ __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, i
 
 // The shared tail slab's share of one Taylor term: vector VT of the last row
 // (RPT-1) only, with the same products as taylor_term for that vector.
-template <typename R, int RPT, int W, int V, int WK, bool AUX, bool SRC1, int VT>
+template <typename R, int RPT, int W, int V, int WK, bool AUX, bool SRC1, int VT, int LR>
 __device__ __forceinline__ void tail_piece(uint32_t base, const SweepArgs& a, int g0,
                                            const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                            const cx<R> (&bv)[RPT][W],
                                            const cx<R> (&ek)[V][RPT][WK], R inv,
                                            cx<R> (&acc)[RPT][V]) {
   using C = cx<R>;
-  using L = Blk<R, RPT, V>;
+  using L = Blk<R, LR, V>;
   constexpr int r = RPT - 1;
   const int d = a.d;
   const uint32_t SRC = SRC1 ? L::bs(d) : 0, DST = SRC1 ? 0 : L::bs(d);
@@ -392,7 +404,7 @@ __device__ __forceinline__ void tail_piece(uint32_t base, const SweepArgs& a, in
   if (ok[r]) lds_st(rb + opaque_s(base + DST) + vo, t);
 }
 
-template <typename R, int RPT, int W, int V, int WK, bool AUX, bool SRC1>
+template <typename R, int RPT, int W, int V, int WK, bool AUX, bool SRC1, int LR>
 __device__ __forceinline__ void tail_share(int tv, uint32_t base, const SweepArgs& a, int g0,
                                            const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                            const cx<R> (&bv)[RPT][W],
@@ -400,16 +412,16 @@ __device__ __forceinline__ void tail_share(int tv, uint32_t base, const SweepArg
                                            cx<R> (&acc)[RPT][V]) {
   switch (tv) {
     case 0:
-      tail_piece<R, RPT, W, V, WK, AUX, SRC1, 0>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      tail_piece<R, RPT, W, V, WK, AUX, SRC1, 0, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
       break;
     case 1:
-      if constexpr (V > 1) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 1>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      if constexpr (V > 1) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 1, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
       break;
     case 2:
-      if constexpr (V > 2) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 2>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      if constexpr (V > 2) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 2, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
       break;
     case 3:
-      if constexpr (V > 3) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 3>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      if constexpr (V > 3) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 3, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
       break;
     default:
       break;
@@ -424,7 +436,7 @@ __device__ __forceinline__ void tail_share(int tv, uint32_t base, const SweepArg
 // `base` is the byte offset of buffer 0, plane 0, row 0.  The term loop is
 // unrolled by two so the buffer being read is a compile-time choice.  Ends
 // with a barrier, so the block may be rewritten right away.
-template <typename R, int RPT, int W, int V, int WK, bool AUX>
+template <typename R, int RPT, int W, int V, int WK, bool AUX, int LR = RPT>
 __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, int g0,
                                              const uint32_t (&rowb)[RPT],
                                              const bool (&ok)[RPT], const bool (&sv)[RPT],
@@ -441,23 +453,23 @@ __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, 
   const bool share = sizeof(R) == 4 && split && V > 1 && tv >= 0;
   constexpr int NRS = RPT > 1 ? RPT - 1 : 1;
   for (int l = 0; l < s; ++l) {
-    block_store<R, RPT, V>(base, a.d, rowb, ok, split, tv, acc);
+    block_store<R, RPT, V, LR>(base, a.d, rowb, ok, split, tv, acc);
     __syncthreads();
     for (int j = 1; j <= m; j += 2) {
-      const R i1 = sgn * inv_int<R>(j);
+      const R i1 = sgn * lds_ld<R>(kInvOff + j * (int)sizeof(R));
       if (full)
-        taylor_term<R, RPT, RPT, W, V, WK, AUX, false>(base, a, g0, rowb, ok, bv, ek, i1, acc);
+        taylor_term<R, RPT, RPT, W, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, i1, acc);
       else
-        taylor_term<R, RPT, NRS, W, V, WK, AUX, false>(base, a, g0, rowb, ok, bv, ek, i1, acc);
-      if (share) tail_share<R, RPT, W, V, WK, AUX, false>(tv, base, a, g0, rowb, ok, bv, ek, i1, acc);
+        taylor_term<R, RPT, NRS, W, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, i1, acc);
+      if (share) tail_share<R, RPT, W, V, WK, AUX, false, LR>(tv, base, a, g0, rowb, ok, bv, ek, i1, acc);
       __syncthreads();
       if (j + 1 <= m) {
-        const R i2 = sgn * inv_int<R>(j + 1);
+        const R i2 = sgn * lds_ld<R>(kInvOff + (j + 1) * (int)sizeof(R));
         if (full)
-          taylor_term<R, RPT, RPT, W, V, WK, AUX, true>(base, a, g0, rowb, ok, bv, ek, i2, acc);
+          taylor_term<R, RPT, RPT, W, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, i2, acc);
         else
-          taylor_term<R, RPT, NRS, W, V, WK, AUX, true>(base, a, g0, rowb, ok, bv, ek, i2, acc);
-        if (share) tail_share<R, RPT, W, V, WK, AUX, true>(tv, base, a, g0, rowb, ok, bv, ek, i2, acc);
+          taylor_term<R, RPT, NRS, W, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, i2, acc);
+        if (share) tail_share<R, RPT, W, V, WK, AUX, true, LR>(tv, base, a, g0, rowb, ok, bv, ek, i2, acc);
         __syncthreads();
       }
     }
@@ -482,10 +494,14 @@ __device__ __forceinline__ void renormalise(cx<R> (&p)[RPT], double* red) {
 // psi_n = (T_m(B_n))^s psi_{n-1} for n = 1..N (Sec. III.B, eq. eBmpsi);
 // penalty partial sum_n <psi_n|Omega|psi_n> (App. A, eq. c2st) and the overlap
 // <phi_T|psi_N> (Sec. III.A) of this column.
-template <typename R, int RPT, int W>
-__global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
+// TPB threads per workgroup; the LDS layout is that of LR = RPT*TPB/512 rows
+// per 512 threads, so the complex64 forward can run 1024 threads (4 waves per
+// SIMD, to hide the latency of its short, barrier-separated terms).
+template <typename R, int RPT, int W, int TPB>
+__global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
   using C = cx<R>;
-  using L = Blk<R, RPT, 1>;
+  constexpr int LR = RPT * TPB / kMaxThreads;
+  using L = Blk<R, LR, 1>;
   double* red = reinterpret_cast<double*>(hg_smem);
   const int d = a.d, tid = threadIdx.x, NT = blockDim.x;
   const int h = blockIdx.x, b = blockIdx.y;
@@ -493,6 +509,7 @@ __global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
   {
     uint32_t* z = reinterpret_cast<uint32_t*>(hg_smem + kRedBytes);
     for (int i = tid; i < L::bytes(d, a.halo) / 4; i += NT) z[i] = 0u;
+    inv_table_to_lds<R>(hg_smem);
   }
   const uint32_t base = kRedBytes + a.halo * L::RB;
 
@@ -527,7 +544,7 @@ __global__ void __launch_bounds__(512) hg_forward(SweepArgs a) {
     const int s = a.ssch[(size_t)b * a.N + n];
     C bv[RPT][W];
     assemble_B<R, RPT, W>(a, ub, n, row, ok, a.dt / (double)s, bv);
-    taylor_block<R, RPT, W, 1, 1, false>(base, a, 0, rowb, ok, sv, false, -1, bv, ek, m, s, (R)1, acc);
+    taylor_block<R, RPT, W, 1, 1, false, LR>(base, a, 0, rowb, ok, sv, false, -1, bv, ek, m, s, (R)1, acc);
     if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
       C p[RPT];
 #pragma unroll
@@ -593,6 +610,7 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
     const int nb = nb1 > nb2 ? nb1 : nb2;
     uint32_t* z = reinterpret_cast<uint32_t*>(hg_smem + kRedBytes);
     for (int i = tid; i < nb / 4; i += NT) z[i] = 0u;
+    inv_table_to_lds<R>(hg_smem);
   }
   // phase 1 block (psi, Lambda) and phase 2 block (Y, X_1..X_G) share the region
   const uint32_t base1 = kRedBytes + a.halo * L1::RB;

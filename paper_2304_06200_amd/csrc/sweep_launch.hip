@@ -132,7 +132,15 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
   // the kernels skip wave slabs past the dimension, which balances the SIMDs
   const int threads = rpt == 1 ? ((dim + 63) / 64) * 64 : kMaxThreads;
   const size_t cs = c128 ? 16 : 8;
-  const size_t fwd = lds_bytes(1, rpt, dim, ops.halo, cs);
+  // complex64 forward above 512 rows: 1024 threads (4 waves per SIMD) with 1 or
+  // 2 rows each; its LDS layout is that of 2*rows per 512 threads
+  int frpt = rpt, fthreads = threads, flr = rpt;
+  if (!c128 && dim > kMaxThreads && dim <= 2 * kMaxFwdThreads && ops.W <= 9) {
+    frpt = (dim + kMaxFwdThreads - 1) / kMaxFwdThreads;
+    fthreads = frpt == 1 ? ((dim + 63) / 64) * 64 : kMaxFwdThreads;
+    flr = frpt * kMaxFwdThreads / kMaxThreads;
+  }
+  const size_t fwd = lds_bytes(1, flr, dim, ops.halo, cs);
   if (fwd > lds_limit) {
     *why = "forward term vectors need " + std::to_string(fwd) + " B of LDS";
     return false;
@@ -153,6 +161,8 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
   sh->n_ctrl = K;
   sh->rows_per_thread = rpt;
   sh->threads = threads;
+  sh->fwd_rows_per_thread = frpt;
+  sh->fwd_threads = fthreads;
   sh->groups = G;
   sh->lds_fwd = fwd;
   sh->lds_bwd = bwd_bytes(G);

@@ -16,7 +16,12 @@ hipError_t run_width_13(const SweepArgs& a, const SweepShape& sh, hipStream_t st
 template <typename R, int RPT, int W, int WK, int G>
 hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream_t st,
                              hipEvent_t* ev) {
-  auto fk = hg_forward<R, RPT, W>;
+  auto fk = hg_forward<R, RPT, W, kMaxThreads>;
+  if constexpr (sizeof(R) == 4 && RPT >= 2 && RPT <= 4 && W <= 9) {
+    if (sh.fwd_threads != sh.threads || sh.fwd_rows_per_thread != RPT)
+      fk = sh.fwd_rows_per_thread == 1 ? hg_forward<R, 1, W, kMaxFwdThreads>
+                                       : hg_forward<R, 2, W, kMaxFwdThreads>;
+  }
   auto bk = hg_backward<R, RPT, W, WK, G>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fk),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_fwd);
@@ -24,9 +29,9 @@ hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(bk),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bwd);
   if (e != hipSuccess) return e;
-  const dim3 grid(sh.n_states, sh.n_batch), block(sh.threads);
+  const dim3 grid(sh.n_states, sh.n_batch), block(sh.threads), fblock(sh.fwd_threads);
   if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(fk, grid, block, sh.lds_fwd, st, a);
+  hipLaunchKernelGGL(fk, grid, fblock, sh.lds_fwd, st, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
