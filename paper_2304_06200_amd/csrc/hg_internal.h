@@ -16,7 +16,7 @@ constexpr int kMaxDiag = 16;      // diagonals of the union pattern (DIA width)
 constexpr int kMaxDiagCtrl = 4;   // diagonals of one control operator
 constexpr int kMaxCtrl = 16;      // control channels
 constexpr int kMaxThreads = 512;  // threads per workgroup (2 waves per SIMD)
-constexpr int kMaxFwdThreads = 1024;  // complex64 forward workgroups (4 waves per SIMD)
+constexpr int kWideThreads = 1024;   // complex64 workgroups for 512 < d <= 2048 (4 waves per SIMD)
 constexpr int kMaxRows = 8;       // rows per thread
 constexpr int kMMax = 60;         // largest Taylor degree the planner may choose
 constexpr int kSMax = 4096;       // largest scaling factor one step may use
@@ -67,7 +67,7 @@ int plan_steps(const double* theta, int64_t n, int sigma, double tau, double u,
 // Kernel launchers (kernels.hip).
 struct SweepShape {
   int dim, n_ctrl, n_steps, n_states, n_batch;
-  int rows_per_thread, threads, groups;  // groups = controls per backward pass
+  int rows_per_thread, threads, groups;  // backward launch; groups = controls per backward pass
   int fwd_rows_per_thread, fwd_threads;  // the forward kernel's own launch shape
   size_t lds_fwd, lds_bwd;
   bool c128;

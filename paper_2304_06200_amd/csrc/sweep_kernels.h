@@ -249,17 +249,22 @@ __device__ __forceinline__ void lds_st(uint32_t off, const T& v) {
   *reinterpret_cast<T*>(hg_smem + off) = v;
 }
 
+// Tail-vector role of a wavefront (see taylor_block): kNotShared for a wave
+// that keeps its own last row slab, else the vector it computes on the shared
+// slab (-1: none).
+constexpr int kNotShared = -2;
+
 // Write the V accumulators of this thread's rows into buffer 0 of the block.
-// With a shared tail slab (see taylor_block) the last row carries only vector
-// tv of this wave (none if tv < 0), written on its own.
+// On a wave of the shared tail slab the last row carries only vector tv
+// (none if tv < 0), written on its own.
 template <typename R, int RPT, int V, int LR = RPT>
 __device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t (&rowb)[RPT],
-                                            const bool (&ok)[RPT], bool split, int tv,
+                                            const bool (&ok)[RPT], int tv,
                                             const cx<R> (&acc)[RPT][V]) {
   using L = Blk<R, LR, V>;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    if (split && r == RPT - 1) {
+    if (tv != kNotShared && r == RPT - 1) {
       if (tv >= 0 && ok[r]) {
         cx<R> x = acc[r][0];
 #pragma unroll
@@ -440,20 +445,20 @@ template <typename R, int RPT, int W, int V, int WK, bool AUX, int LR = RPT>
 __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, int g0,
                                              const uint32_t (&rowb)[RPT],
                                              const bool (&ok)[RPT], const bool (&sv)[RPT],
-                                             bool split, int tv,
+                                             int tv,
                                              const cx<R> (&bv)[RPT][W],
                                              const cx<R> (&ek)[V][RPT][WK], int m, int s, R sgn,
                                              cx<R> (&acc)[RPT][V]) {
   // A wavefront whose last row slab lies past the dimension runs the RPT-1 row
-  // variant (wave-uniform choice, both variants fully unrolled).  With a shared
-  // tail slab (`split`: the last plane holds a single slab), every wavefront
-  // runs RPT-1 rows and the tail's vectors are spread over the wavefronts of
-  // different SIMDs: vector tv by this one (V == 1: the whole tail if tv == 0).
-  const bool full = split ? (V == 1 && tv == 0) : sv[RPT - 1];
-  const bool share = sizeof(R) == 4 && split && V > 1 && tv >= 0;
+  // variant (wave-uniform choice, both variants fully unrolled).  The waves of
+  // a shared tail slab (tv != kNotShared: four waves on different SIMDs) run
+  // RPT-1 rows and split that slab by vector: vector tv by this one (V == 1:
+  // the whole slab if tv == 0).
+  const bool full = tv == kNotShared ? sv[RPT - 1] : (V == 1 && tv == 0);
+  const bool share = sizeof(R) == 4 && V > 1 && tv >= 0;
   constexpr int NRS = RPT > 1 ? RPT - 1 : 1;
   for (int l = 0; l < s; ++l) {
-    block_store<R, RPT, V, LR>(base, a.d, rowb, ok, split, tv, acc);
+    block_store<R, RPT, V, LR>(base, a.d, rowb, ok, tv, acc);
     __syncthreads();
     for (int j = 1; j <= m; j += 2) {
       const R i1 = sgn * lds_ld<R>(kInvOff + j * (int)sizeof(R));
@@ -544,7 +549,7 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
     const int s = a.ssch[(size_t)b * a.N + n];
     C bv[RPT][W];
     assemble_B<R, RPT, W>(a, ub, n, row, ok, a.dt / (double)s, bv);
-    taylor_block<R, RPT, W, 1, 1, false, LR>(base, a, 0, rowb, ok, sv, false, -1, bv, ek, m, s, (R)1, acc);
+    taylor_block<R, RPT, W, 1, 1, false, LR>(base, a, 0, rowb, ok, sv, kNotShared, bv, ek, m, s, (R)1, acc);
     if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
       C p[RPT];
 #pragma unroll
@@ -595,12 +600,15 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
 //   Lambda_{n-1} = Lambda' + (w_pen/(N S)) Omega psi_{n-1}   for n-1 >= 1 (App. A)
 // Controls are processed in groups of G (the bottom block Y is recomputed per
 // group) so that the (1+G)-vector double-buffered block fits in LDS.
-template <typename R, int RPT, int W, int WK, int G>
-__global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
+// TPB threads per workgroup, LDS layout of LR = RPT*TPB/512 rows per 512
+// threads (as in the forward kernel).
+template <typename R, int RPT, int W, int WK, int G, int TPB>
+__global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   using C = cx<R>;
   constexpr int V2 = 1 + G;
-  using L1 = Blk<R, RPT, 2>;
-  using L2 = Blk<R, RPT, V2>;
+  constexpr int LR = RPT * TPB / kMaxThreads;
+  using L1 = Blk<R, LR, 2>;
+  using L2 = Blk<R, LR, V2>;
   double* red = reinterpret_cast<double*>(hg_smem);
   const int d = a.d, tid = threadIdx.x, NT = blockDim.x, K = a.K, N = a.N, S = a.S;
   const int h = blockIdx.x, b = blockIdx.y;
@@ -621,16 +629,21 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
   C* const c_lam = cold + d;      // propagated co-state
   C* const c_cur = cold + 2 * d;  // Lambda_n (for the overlaps)
 
-  // Shared tail slab: when the last plane of rows holds one slab (at most 64
-  // rows), wavefronts 0..3 (one per SIMD) all map their last row to it and
-  // own one vector each there: psi -> 0, Lambda -> 1 in phase 1, Y -> 0 and
-  // X_v -> v in phase 2.  A thread's copy of a tail vector it does not own
+  // Shared tail slab: the last plane of rows holds T slabs of 64 rows.  With
+  // T = 4q+1 the last one (index ts = T-1) would leave one SIMD a slab more
+  // than the others; instead waves ts..ts+3 (one per SIMD; their own slabs of
+  // that plane lie past the dimension) all map their last row to it and own
+  // one vector each there: psi -> ts, Lambda -> ts+1 in phase 1, Y -> ts and
+  // X_v -> ts+v in phase 2.  A thread's copy of a tail vector it does not own
   // stays zero, so sums over rows need no extra test; stores are guarded.
   // (complex64 only: the complex128 kernels have no registers to spare for it)
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tail0 = (RPT - 1) * NT;
-  const bool split = sizeof(R) == 4 && RPT > 1 && d > tail0 && d - tail0 <= 64;
-  const bool tailw = split && wv < 4;
+  const int T = d > tail0 ? (d - tail0 + 63) / 64 : 0;
+  const int ts = T - 1;
+  const bool split = sizeof(R) == 4 && RPT > 1 && T % 4 == 1 && ts + 4 <= NT / 64;
+  const bool tailw = split && wv >= ts && wv < ts + 4;
+  const int tw = wv - ts;  // this wave's index in the sharing group
 
   int row[RPT];
   uint32_t rowb1[RPT], rowb2[RPT];
@@ -661,11 +674,11 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
   const double fr = -a.w_fid * gre / S, fi = -a.w_fid * gim / S;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const bool shared = split && r == RPT - 1;
-    const int i = (shared && tailw) ? tail0 + (tid & 63) : tid + r * NT;
+    const bool shared = tailw && r == RPT - 1;
+    const int i = shared ? tail0 + ts * 64 + (tid & 63) : tid + r * NT;
     ok[r] = i < d;
-    own_psi[r] = ok[r] && (!shared || wv == 0);
-    own_lam[r] = ok[r] && (!shared || wv == 1);
+    own_psi[r] = ok[r] && (!shared || tw == 0);
+    own_lam[r] = ok[r] && (!shared || tw == 1);
     row[r] = ok[r] ? i : d - 1;
     rowb1[r] = (uint32_t)row[r] * L1::RB;
     rowb2[r] = (uint32_t)row[r] * L2::RB;
@@ -679,10 +692,10 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
   __syncthreads();
   // tail vector of this wavefront in the phase-1 block, the phase-2 block and
   // the single-vector blocks of psi and of Lambda
-  const int tv1 = tailw && wv < 2 ? wv : -1;
-  const int tv2 = tailw && wv < V2 ? wv : -1;
-  const int tvp = tailw && wv == 0 ? 0 : -1;
-  const int tvl = tailw && wv == 1 ? 0 : -1;
+  const int tv1 = !tailw ? kNotShared : tw < 2 ? tw : -1;
+  const int tv2 = !tailw ? kNotShared : tw < V2 ? tw : -1;
+  const int tvp = !tailw ? kNotShared : tw == 0 ? 0 : -1;
+  const int tvl = !tailw ? kNotShared : tw == 1 ? 0 : -1;
 
   C ek1[2][RPT][1];
   const double* ub = a.u + (size_t)b * K * N;
@@ -693,7 +706,7 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
   const bool ckpt = a.ckpt_every > 0;
   const int CK = ckpt ? a.ckpt_every : N;
   const int nseg = (N + CK - 1) / CK;
-  using LF = Blk<R, RPT, 1>;
+  using LF = Blk<R, LR, 1>;
   const uint32_t basef = kRedBytes + a.halo * LF::RB;
   uint32_t rowbf[RPT];
 #pragma unroll
@@ -717,7 +730,7 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
       C bv[RPT][W];
       assemble_B<R, RPT, W>(a, ub, n, row, ok, a.dt / (double)s, bv);
       C ekf[1][RPT][1];
-      taylor_block<R, RPT, W, 1, 1, false>(basef, a, 0, rowbf, ok, sv, split, tvp, bv, ekf, m, s,
+      taylor_block<R, RPT, W, 1, 1, false, LR>(basef, a, 0, rowbf, ok, sv, tvp, bv, ekf, m, s,
                                            (R)1, f);
       if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
         C p[RPT];
@@ -741,7 +754,7 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
 
     if (!ckpt) {
       // phase 1: psi and Lambda through (T_m(-B))^s together
-      taylor_block<R, RPT, W, 2, 1, false>(base1, a, 0, rowb1, ok, sv, split, tv1, bv, ek1, m, s,
+      taylor_block<R, RPT, W, 2, 1, false, LR>(base1, a, 0, rowb1, ok, sv, tv1, bv, ek1, m, s,
                                            (R)-1, pl);
       if (a.renorm_every > 0 && n % a.renorm_every == 0) {
         C p[RPT];
@@ -763,7 +776,7 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r) lm[r][0] = pl[r][1];
       C ekf[1][RPT][1];
-      taylor_block<R, RPT, W, 1, 1, false>(basef, a, 0, rowbf, ok, sv, split, tvl, bv, ekf, m, s,
+      taylor_block<R, RPT, W, 1, 1, false, LR>(basef, a, 0, rowbf, ok, sv, tvl, bv, ekf, m, s,
                                            (R)-1, lm);
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
@@ -785,12 +798,12 @@ __global__ void __launch_bounds__(512) hg_backward(SweepArgs a) {
       C yx[RPT][V2];
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        // Y starts from psi_{n-1}: on the shared tail only its owner (wave 0)
+        // Y starts from psi_{n-1}: on the shared tail only its psi owner
         yx[r][0] = own_psi[r] ? c_psi[opaque(row[r])] : C{(R)0, (R)0};
 #pragma unroll
         for (int v = 1; v < V2; ++v) yx[r][v] = C{(R)0, (R)0};
       }
-      taylor_block<R, RPT, W, V2, WK, true>(base2, a, g0, rowb2, ok, sv, split, tv2, bv, ek, m, s,
+      taylor_block<R, RPT, W, V2, WK, true, LR>(base2, a, g0, rowb2, ok, sv, tv2, bv, ek, m, s,
                                             (R)1, yx);
       double gv[G];
 #pragma unroll

@@ -130,15 +130,24 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
   }
   // one row per thread below 512 rows; above, 8 full waves (2 per SIMD) and
   // the kernels skip wave slabs past the dimension, which balances the SIMDs
-  const int threads = rpt == 1 ? ((dim + 63) / 64) * 64 : kMaxThreads;
+  int threads = rpt == 1 ? ((dim + 63) / 64) * 64 : kMaxThreads;
   const size_t cs = c128 ? 16 : 8;
-  // complex64 forward above 512 rows: 1024 threads (4 waves per SIMD) with 1 or
-  // 2 rows each; its LDS layout is that of 2*rows per 512 threads
-  int frpt = rpt, fthreads = threads, flr = rpt;
-  if (!c128 && dim > kMaxThreads && dim <= 2 * kMaxFwdThreads && ops.W <= 9) {
-    frpt = (dim + kMaxFwdThreads - 1) / kMaxFwdThreads;
-    fthreads = frpt == 1 ? ((dim + 63) / 64) * 64 : kMaxFwdThreads;
-    flr = frpt * kMaxFwdThreads / kMaxThreads;
+  // complex64 above 512 rows (up to 2048): 1024 threads (4 waves per SIMD, to
+  // hide the latency around each term's barrier) with 1 or 2 rows each; the
+  // LDS layout is that of 2*rows per 512 threads.  The forward always, the
+  // backward when its controls have at most 2 diagonals (register budget).
+  int wk = 1;
+  for (int k = 0; k < K; ++k) wk = std::max(wk, ops.WK[k]);
+  int frpt = rpt, fthreads = threads, flr = rpt, blr = rpt;
+  if (!c128 && dim > kMaxThreads && dim <= 2 * kWideThreads && ops.W <= 9) {
+    frpt = (dim + kWideThreads - 1) / kWideThreads;
+    fthreads = frpt == 1 ? ((dim + 63) / 64) * 64 : kWideThreads;
+    flr = frpt * kWideThreads / kMaxThreads;
+    if (wk <= 2) {
+      rpt = frpt;
+      threads = fthreads;
+      blr = flr;
+    }
   }
   const size_t fwd = lds_bytes(1, flr, dim, ops.halo, cs);
   if (fwd > lds_limit) {
@@ -150,7 +159,7 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
   int G = 1;
   if (!c128 && K >= 2) G = (K % 3 == 0) ? 3 : (K % 2 == 0) ? 2 : (K >= 3 ? 3 : 2);
   auto bwd_bytes = [&](int g) {
-    return std::max(lds_bytes(2, rpt, dim, ops.halo, cs), lds_bytes(g + 1, rpt, dim, ops.halo, cs));
+    return std::max(lds_bytes(2, blr, dim, ops.halo, cs), lds_bytes(g + 1, blr, dim, ops.halo, cs));
   };
   while (G > 1 && bwd_bytes(G) > lds_limit) --G;
   if (bwd_bytes(G) > lds_limit) {

@@ -17,12 +17,15 @@ template <typename R, int RPT, int W, int WK, int G>
 hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream_t st,
                              hipEvent_t* ev) {
   auto fk = hg_forward<R, RPT, W, kMaxThreads>;
-  if constexpr (sizeof(R) == 4 && RPT >= 2 && RPT <= 4 && W <= 9) {
-    if (sh.fwd_threads != sh.threads || sh.fwd_rows_per_thread != RPT)
-      fk = sh.fwd_rows_per_thread == 1 ? hg_forward<R, 1, W, kMaxFwdThreads>
-                                       : hg_forward<R, 2, W, kMaxFwdThreads>;
+  auto bk = hg_backward<R, RPT, W, WK, G, kMaxThreads>;
+  if constexpr (sizeof(R) == 4 && RPT <= 4 && W <= 9) {
+    if (sh.fwd_threads > kMaxThreads)
+      fk = sh.fwd_rows_per_thread == 1 ? hg_forward<R, 1, W, kWideThreads>
+                                       : hg_forward<R, 2, W, kWideThreads>;
   }
-  auto bk = hg_backward<R, RPT, W, WK, G>;
+  if constexpr (sizeof(R) == 4 && RPT <= 2 && W <= 9 && WK <= 2) {
+    if (sh.threads > kMaxThreads) bk = hg_backward<R, RPT, W, WK, G, kWideThreads>;
+  }
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fk),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_fwd);
   if (e != hipSuccess) return e;
