@@ -132,18 +132,18 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
   // the kernels skip wave slabs past the dimension, which balances the SIMDs
   int threads = rpt == 1 ? ((dim + 63) / 64) * 64 : kMaxThreads;
   const size_t cs = c128 ? 16 : 8;
-  // complex64 above 512 rows (up to 2048): 1024 threads (4 waves per SIMD, to
-  // hide the latency around each term's barrier) with 1 or 2 rows each; the
-  // LDS layout is that of 2*rows per 512 threads.  The forward always, the
-  // backward when its controls have at most 2 diagonals (register budget).
+  // Above 512 rows (up to 2048): 1024 threads (4 waves per SIMD, to hide the
+  // latency around each term's barrier) with 1 or 2 rows each; the LDS layout
+  // is that of 2*rows per 512 threads.  The forward always, the backward in
+  // complex64 when its controls have at most 2 diagonals (register budget).
   int wk = 1;
   for (int k = 0; k < K; ++k) wk = std::max(wk, ops.WK[k]);
   int frpt = rpt, fthreads = threads, flr = rpt, blr = rpt;
-  if (!c128 && dim > kMaxThreads && dim <= 2 * kWideThreads && ops.W <= 9) {
+  if (dim > kMaxThreads && dim <= 2 * kWideThreads && ops.W <= 9) {
     frpt = (dim + kWideThreads - 1) / kWideThreads;
     fthreads = frpt == 1 ? ((dim + 63) / 64) * 64 : kWideThreads;
     flr = frpt * kWideThreads / kMaxThreads;
-    if (wk <= 2) {
+    if (!c128 && wk <= 2) {
       rpt = frpt;
       threads = fthreads;
       blr = flr;

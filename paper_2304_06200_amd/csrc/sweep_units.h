@@ -18,7 +18,7 @@ hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream
                              hipEvent_t* ev) {
   auto fk = hg_forward<R, RPT, W, kMaxThreads>;
   auto bk = hg_backward<R, RPT, W, WK, G, kMaxThreads>;
-  if constexpr (sizeof(R) == 4 && RPT <= 4 && W <= 9) {
+  if constexpr (RPT <= 4 && W <= 9) {
     if (sh.fwd_threads > kMaxThreads)
       fk = sh.fwd_rows_per_thread == 1 ? hg_forward<R, 1, W, kWideThreads>
                                        : hg_forward<R, 2, W, kWideThreads>;
