@@ -293,10 +293,10 @@ __device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t
 // LDS reads in flight ahead of the FMAs that consume them, and a scheduling
 // barrier after each item pins that order.  Items run row by row: first the W
 // union diagonals (NP plane-row reads each), then for AUX the (V-1)*WK
-// derivative operand reads (the Y entry only).  Single-vector blocks keep all
-// RPT*W gather addresses in registers (computed once per kernel); multi-vector
-// blocks rebuild each from one per-row base with one add, which keeps the
-// register budget for the extra accumulators.
+// derivative operand reads (the Y entry only).  Each gather address is one
+// add of a per-row base (VGPR) and the diagonal's offset (SGPR); keeping all
+// RPT*W addresses in registers instead spills at these register budgets and
+// did not make the forward kernel faster.
 template <typename R, int RPT, int NR, int W, int V, int WK, bool AUX, bool SRC1, int LR = RPT>
 __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, int g0,
                                             const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
