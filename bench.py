@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # more hardware queues than HIP's default of 4, so the serving loop's concurrent
 # request streams can run side by side (must be set before HIP initialises)
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "32")
 
 METRIC = "cost+gradient evals/s (dim 1600, N=2000, 16 states) c64 vs c128; p99 ms served"
 PEAK_VALU_TFLOPS = 78.6  # unpacked FP32 FMA and FP64 FMA: 256 CU x 64 lanes x 2 flop x 2.4 GHz
@@ -84,11 +84,11 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"].strip())
 
 
-def serving(hg, ctx, dtype, n_req, inflight, budget, load=0.7, seed=4):
+def serving(hg, ctx, dtype, n_req, inflight, budget, qps, seed=4):
     """cfg4 stream: n_req requests of transmon(3) x cavity(d_c) problems, d_c
     log-uniform in [8, 700], N in [200, 2000], S in [1, 8].  First all at once
-    (saturated throughput X), then Poisson arrivals at load*X; latency is
-    submit-to-finish per request."""
+    (saturated throughput), then Poisson arrivals at a fixed rate `qps` (the
+    same for both precisions); latency is submit-to-finish per request."""
     import numpy as np
     import torch
     from workloads.configs import serving_request, serving_stream
@@ -111,7 +111,7 @@ def serving(hg, ctx, dtype, n_req, inflight, budget, load=0.7, seed=4):
         sv.wait(h)
     sat = n_req / (time.perf_counter() - t0)
     log(f"  serving {dtype}: saturated {sat:.2f} req/s")
-    rate = load * sat
+    rate = qps
     rng = np.random.default_rng(seed + 1000)
     gaps = rng.exponential(1.0 / rate, size=n_req)
     hs = []
@@ -162,7 +162,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
-    ap.add_argument("--serve-inflight", type=int, default=16)
+    ap.add_argument("--serve-inflight", type=int, default=32)
+    ap.add_argument("--serve-qps", type=float, default=4.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for the "
@@ -244,11 +245,11 @@ def main():
         budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)
         line["served"] = {
             "workload": "cfg4: transmon(3) x cavity(d_c log-uniform 8..700), N 200..2000, S 1..8, "
-                        "dt=1 ns, tau=1e-10, Poisson arrivals at 0.7 x saturated rate",
+                        f"dt=1 ns, tau=1e-10, Poisson arrivals at {args.serve_qps:g} req/s",
             "requests": args.serve_requests, "slots": args.serve_inflight, "hbm_budget_bytes": budget}
         for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
             line["served"][dtype] = serving(hg, ctx, dtype, args.serve_requests,
-                                            args.serve_inflight, budget)
+                                            args.serve_inflight, budget, args.serve_qps)
         line["served"]["p99_ms"] = line["served"]["c64"]["p99_ms"]
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {args.cpu_sample} steps")

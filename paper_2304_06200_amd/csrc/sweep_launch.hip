@@ -139,7 +139,9 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
   int wk = 1;
   for (int k = 0; k < K; ++k) wk = std::max(wk, ops.WK[k]);
   int frpt = rpt, fthreads = threads, flr = rpt, blr = rpt;
-  if (dim > kMaxThreads && dim <= 2 * kWideThreads && ops.W <= 9) {
+  const bool wide = dim > kMaxThreads && ((dim <= 2 * kWideThreads && ops.W <= 9) ||
+                                          (dim <= 3 * kWideThreads && ops.W <= 5));
+  if (wide) {
     frpt = (dim + kWideThreads - 1) / kWideThreads;
     fthreads = frpt == 1 ? ((dim + 63) / 64) * 64 : kWideThreads;
     flr = frpt * kWideThreads / kMaxThreads;
@@ -161,6 +163,8 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
   auto bwd_bytes = [&](int g) {
     return std::max(lds_bytes(2, blr, dim, ops.halo, cs), lds_bytes(g + 1, blr, dim, ops.halo, cs));
   };
+  // 3 rows per thread at 1024 threads leaves registers for two controls per pass
+  if (!c128 && threads > kMaxThreads && rpt == 3 && G > 2) G = 2;
   while (G > 1 && bwd_bytes(G) > lds_limit) --G;
   if (bwd_bytes(G) > lds_limit) {
     *why = "backward state block does not fit in LDS";

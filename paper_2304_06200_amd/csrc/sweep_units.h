@@ -18,12 +18,14 @@ hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream
                              hipEvent_t* ev) {
   auto fk = hg_forward<R, RPT, W, kMaxThreads>;
   auto bk = hg_backward<R, RPT, W, WK, G, kMaxThreads>;
-  if constexpr (RPT <= 4 && W <= 9) {
-    if (sh.fwd_threads > kMaxThreads)
-      fk = sh.fwd_rows_per_thread == 1 ? hg_forward<R, 1, W, kWideThreads>
-                                       : hg_forward<R, 2, W, kWideThreads>;
+  if constexpr (W <= 9 && RPT <= (W <= 5 ? 6 : 4)) {
+    if (sh.fwd_threads > kMaxThreads) {
+      if (sh.fwd_rows_per_thread == 1) fk = hg_forward<R, 1, W, kWideThreads>;
+      else if (sh.fwd_rows_per_thread == 2) fk = hg_forward<R, 2, W, kWideThreads>;
+      else if constexpr (W <= 5) fk = hg_forward<R, 3, W, kWideThreads>;
+    }
   }
-  if constexpr (sizeof(R) == 4 && RPT <= 2 && W <= 9 && WK <= 2) {
+  if constexpr (sizeof(R) == 4 && WK <= 2 && (RPT <= 2 || (RPT == 3 && W <= 5 && G <= 2))) {
     if (sh.threads > kMaxThreads) bk = hg_backward<R, RPT, W, WK, G, kWideThreads>;
   }
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fk),

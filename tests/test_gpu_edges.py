@@ -69,6 +69,20 @@ def test_large_ragged_dimensions(d):
         assert_parity(run(p, dt), ref, dt, label=f"osc{d}")
 
 
+def test_wide_pattern_above_2048_rows():
+    """Nine-diagonal cfg3 structure with a 177-level cavity (d = 2832): 512
+    threads with 6 rows each and a last plane of 5 row slabs (the fifth shared
+    by vector); three steps against the discretised oracle, complex64."""
+    from gpu_common import oracle_schedule
+    from oracle import taylor
+    p = make_config("cfg3", N=3, d_c=177)
+    sched = oracle_schedule(p)
+    ref = taylor.hg_discrete(p.H0, p.Hk, p.u, p.dt, p.psi0, p.targets, sched, omega=p.omega,
+                             w_fid=p.w_fid, w_pen=p.w_pen)
+    log(f"[case] cfg3 structure d={p.dim}, sum_mu {int(np.sum(sched[0] * sched[1]))}")
+    assert_parity(run(p, "c64"), ref, "c64", label=f"cfg3c177")
+
+
 def test_single_step_single_state_no_penalty():
     p = _cavity_problem(10, K=1, N=1, S=1, penalty=False)
     log("[case] N=1 S=1 K=1 no penalty")
