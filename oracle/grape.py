@@ -10,14 +10,20 @@ Notation follows the paper (arXiv:2304.06200):
           tr(U_T^dag U_R)/d when the S states are a full basis, eq. gategradient)
   C1    = 1 - |g|^2                                 Sec. III.A, eq. C1st
   C2    = 1/(N S) sum_h sum_{n'=1..N} <psi_n'|Omega|psi_n'>   App. A, eq. c2st
-  C     = w_fid C1 + w_pen C2                       Sec. II (composite cost)
+  g_n   = (1/S) sum_h <phi_T^h | psi_n^h>           (overlap after step n)
+  C3    = 1 - (1/N) sum_{n'=1..N} |g_n'|^2          App. A (time-integrated
+          infidelity: C3^st for S=1, C3^g when the S states are a full basis)
+  C     = w_fid C1 + w_pen C2 + w_int C3            Sec. II (composite cost)
 
-Gradient (Sec. III.A eqs. stgradient / gategradient, App. A eq. C2stgrad):
+Gradient (Sec. III.A eqs. stgradient / gategradient, App. A eqs. C2stgrad and
+state time gradient):
   dC/du[k,n] = 2 Re sum_h <Lambda_n^h | dU_n/du_k | psi_{n-1}^h>
-  Lambda_N   = -(w_fid g / S) phi_T + (w_pen/(N S)) Omega psi_N
-  Lambda_n-1 = U_n^dag Lambda_n + (w_pen/(N S)) Omega psi_{n-1}   (n-1 >= 1)
+  Lambda_N   = -(w_fid g / S) phi_T + src_N
+  Lambda_n-1 = U_n^dag Lambda_n + src_{n-1}                         (n-1 >= 1)
+  src_n      = (w_pen/(N S)) Omega psi_n - (w_int/(N S)) g_n phi_T
 The fidelity part is eq. stgradient with the factor conj(g) folded into the
-co-state (linearity); the penalty part is the Phi_n recursion of App. A.
+co-state (linearity); the penalty part is the Phi_n recursion of App. A, the
+time-integrated part its Phi_{T,n} recursion (one source per step).
 dU_n/du_k is the Frechet derivative L(A_n, E_k) of expm at A_n = -i dt H_n in
 direction E_k = -i dt h_k.
 
@@ -102,9 +108,16 @@ def forward_states(H0, Hk, u, dt, psi0) -> np.ndarray:
     return psi
 
 
+def step_overlaps(psi: np.ndarray, targets: np.ndarray) -> np.ndarray:
+    """g_n = (1/S) sum_h <phi_T^h | psi_n^h> for n = 0..N (complex, (N+1,))."""
+    S = psi.shape[2]
+    return np.einsum("hd,ndh->n", np.conj(targets), psi) / S
+
+
 def cost_terms(psi: np.ndarray, targets: np.ndarray, omega: Optional[np.ndarray],
-               w_fid: float, w_pen: float):
-    """Cost parts from stored states (Sec. III.A eq. C1st; App. A eq. c2st)."""
+               w_fid: float, w_pen: float, w_int: float = 0.0):
+    """Cost parts from stored states (Sec. III.A eq. C1st; App. A eq. c2st and
+    the time-integrated infidelity).  Returns g, C1, C2, C3, C."""
     N = psi.shape[0] - 1
     S = psi.shape[2]
     g = np.sum(np.conj(targets.T) * psi[N]) / S
@@ -114,11 +127,13 @@ def cost_terms(psi: np.ndarray, targets: np.ndarray, omega: Optional[np.ndarray]
         C2 = float(occ) / (N * S)
     else:
         C2 = 0.0
-    return g, C1, C2, w_fid * C1 + w_pen * C2
+    gn = step_overlaps(psi, targets)
+    C3 = 1.0 - float(np.sum(np.abs(gn[1:]) ** 2)) / N
+    return g, C1, C2, C3, w_fid * C1 + w_pen * C2 + w_int * C3
 
 
 def cost_and_grad(H0, Hk, u, dt, psi0, targets, omega=None, w_fid=1.0, w_pen=0.0,
-                  frechet: str = "eig", want_states: bool = False) -> dict:
+                  frechet: str = "eig", want_states: bool = False, w_int: float = 0.0) -> dict:
     """Exact cost and gradient of the composite cost (oracle).
 
     H0, Hk   drift and control operators (dense or scipy.sparse), (d, d)
@@ -127,8 +142,9 @@ def cost_and_grad(H0, Hk, u, dt, psi0, targets, omega=None, w_fid=1.0, w_pen=0.0
     omega    (d,) diagonal of the Hermitian penalty operator Omega, or None
     frechet  "eig" (Daleckii-Krein in the eigenbasis of H_n, App. F) or
              "block" (Van Loan block exponential, Sec. III.B identity)
-    Returns a dict with cost, infidelity (C1), penalty (C2), overlap g,
-    grad (K, N) and, on request, the stored states.
+    w_int    weight of the time-integrated infidelity C3 (App. A)
+    Returns a dict with cost, infidelity (C1), penalty (C2), integrated
+    infidelity (C3), overlap g, grad (K, N) and, on request, the stored states.
     """
     u = np.asarray(u, dtype=np.float64)
     K, N = u.shape
@@ -141,12 +157,20 @@ def cost_and_grad(H0, Hk, u, dt, psi0, targets, omega=None, w_fid=1.0, w_pen=0.0
     om = None if omega is None else np.asarray(omega, dtype=np.float64)
 
     psi = forward_states(H0d, Hkd, u, dt, psi0)
-    g, C1, C2, C = cost_terms(psi, targets, om, w_fid, w_pen)
+    g, C1, C2, C3, C = cost_terms(psi, targets, om, w_fid, w_pen, w_int)
+    gn = step_overlaps(psi, targets)
 
     cpen = (w_pen / (N * S)) if om is not None else 0.0
-    lam = -(w_fid * g / S) * targets.T.copy()
-    if om is not None:
-        lam = lam + cpen * om[:, None] * psi[N]
+    cint = w_int / (N * S)
+
+    def source(n):
+        # co-state source of step n: penalty (Phi_n) and time-integrated (Phi_T,n)
+        src = -cint * gn[n] * targets.T
+        if om is not None:
+            src = src + cpen * om[:, None] * psi[n]
+        return src
+
+    lam = -(w_fid * g / S) * targets.T.copy() + source(N)
 
     E = [-1j * dt * h for h in Hkd]
     grad = np.zeros((K, N), dtype=np.float64)
@@ -169,27 +193,27 @@ def cost_and_grad(H0, Hk, u, dt, psi0, targets, omega=None, w_fid=1.0, w_pen=0.0
             for k in range(K):
                 grad[k, n - 1] = 2.0 * np.real(np.sum(E[k] * Q.T))
         if n - 1 >= 1:
-            # Lambda_{n-1} = U_n^dag Lambda_n (+ penalty source), U_n^dag = V e^{+i dt w} V^dag
-            lam = V @ (np.exp(1j * dt * w)[:, None] * (V.conj().T @ lam))
-            if om is not None:
-                lam = lam + cpen * om[:, None] * prev
+            # Lambda_{n-1} = U_n^dag Lambda_n + src_{n-1}, U_n^dag = V e^{+i dt w} V^dag
+            lam = V @ (np.exp(1j * dt * w)[:, None] * (V.conj().T @ lam)) + source(n - 1)
     out = {"cost": float(C), "infidelity": float(C1), "penalty": float(C2),
-           "overlap": complex(g), "grad": grad}
+           "integrated_infidelity": float(C3), "overlap": complex(g), "grad": grad}
     if want_states:
         out["states"] = psi
     return out
 
 
-def cost_only(H0, Hk, u, dt, psi0, targets, omega=None, w_fid=1.0, w_pen=0.0) -> float:
+def cost_only(H0, Hk, u, dt, psi0, targets, omega=None, w_fid=1.0, w_pen=0.0,
+              w_int=0.0) -> float:
     """The composite cost alone (used by finite-difference pins)."""
     psi = forward_states(H0, Hk, np.asarray(u, dtype=np.float64), dt,
                          np.asarray(psi0, dtype=np.complex128))
     om = None if omega is None else np.asarray(omega, dtype=np.float64)
     return float(cost_terms(psi, np.asarray(targets, dtype=np.complex128), om,
-                            w_fid, w_pen)[3])
+                            w_fid, w_pen, w_int)[4])
 
 
-def gradient_brute_force(H0, Hk, u, dt, psi0, targets, omega=None, w_fid=1.0, w_pen=0.0):
+def gradient_brute_force(H0, Hk, u, dt, psi0, targets, omega=None, w_fid=1.0, w_pen=0.0,
+                         w_int=0.0):
     """Gradient by the explicit chain-rule sums, without any co-state recursion:
     d psi_n'/du[k,n] = U_n' ... U_{n+1} L(A_n, E_k) psi_{n-1} for n' >= n (the
     first lines of eqs. stgradient and C2stgrad).  O(N^2) products: tiny cases only."""
@@ -202,7 +226,8 @@ def gradient_brute_force(H0, Hk, u, dt, psi0, targets, omega=None, w_fid=1.0, w_
     S = psi0.shape[0]
     om = None if omega is None else np.asarray(omega, dtype=np.float64)
     psi = forward_states(H0d, Hkd, u, dt, psi0)
-    g, _, _, _ = cost_terms(psi, targets, om, w_fid, w_pen)
+    g = cost_terms(psi, targets, om, w_fid, w_pen, w_int)[0]
+    gn = step_overlaps(psi, targets)
     Hs = [hamiltonian(H0d, Hkd, u[:, n]) for n in range(N)]
     Us = [propagator(H, dt) for H in Hs]
     grad = np.zeros((K, N))
@@ -217,6 +242,10 @@ def gradient_brute_force(H0, Hk, u, dt, psi0, targets, omega=None, w_fid=1.0, w_
                 if om is not None and w_pen != 0.0:
                     total += w_pen / (N * S) * 2.0 * np.real(
                         np.sum(np.conj(psi[npr]) * (om[:, None] * dpsi)))
+                if w_int != 0.0:
+                    # d|g_n'|^2 = 2 Re conj(g_n') dg_n'
+                    dgn = np.sum(np.conj(targets.T) * dpsi) / S
+                    total -= w_int / N * 2.0 * np.real(np.conj(gn[npr]) * dgn)
             dg = np.sum(np.conj(targets.T) * dpsi) / S
             total += w_fid * (-2.0 * np.real(np.conj(g) * dg))
             grad[k, n - 1] = total

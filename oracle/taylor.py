@@ -58,7 +58,7 @@ def aux_action(A, E, psi: np.ndarray, m: int, s: int):
 
 
 def hg_discrete(H0, Hk: Sequence, u, dt, psi0, targets, schedule, omega=None,
-                w_fid=1.0, w_pen=0.0) -> dict:
+                w_fid=1.0, w_pen=0.0, w_int=0.0) -> dict:
     """Cost and gradient of the Taylor-discretised problem (oracle).
 
     schedule: (2, N) int array, rows m_n and s_n.  The cost is the composite
@@ -94,10 +94,19 @@ def hg_discrete(H0, Hk: Sequence, u, dt, psi0, targets, schedule, omega=None,
     else:
         om = None
         C2 = 0.0
+    # time-integrated infidelity C3 = 1 - (1/N) sum_n |g_n|^2 (App. A)
+    gn = [np.sum(np.conj(targets.T) * psi[n]) / S for n in range(N + 1)]
+    C3 = 1.0 - sum(abs(gn[n]) ** 2 for n in range(1, N + 1)) / N
     cpen = (w_pen / (N * S)) if om is not None else 0.0
-    lam = -(w_fid * g / S) * targets.T
-    if om is not None:
-        lam = lam + cpen * om[:, None] * psi[N]
+    cint = w_int / (N * S)
+
+    def source(n):
+        src = -cint * gn[n] * targets.T
+        if om is not None:
+            src = src + cpen * om[:, None] * psi[n]
+        return src
+
+    lam = -(w_fid * g / S) * targets.T + source(N)
     grad = np.zeros((K, N))
     for n in range(N, 0, -1):
         A = A_of(n)
@@ -106,9 +115,7 @@ def hg_discrete(H0, Hk: Sequence, u, dt, psi0, targets, schedule, omega=None,
             X, _ = aux_action(A, -1j * dt * Hk[k], psi[n - 1], m, s)
             grad[k, n - 1] = 2.0 * np.real(np.sum(np.conj(lam) * X))
         if n - 1 >= 1:
-            lam = taylor_action(-A, lam, m, s)
-            if om is not None:
-                lam = lam + cpen * om[:, None] * psi[n - 1]
-    return {"cost": float(w_fid * C1 + w_pen * C2), "infidelity": float(C1),
-            "penalty": float(C2), "overlap": complex(g), "grad": grad,
-            "final_states": psi[N].T.copy()}
+            lam = taylor_action(-A, lam, m, s) + source(n - 1)
+    return {"cost": float(w_fid * C1 + w_pen * C2 + w_int * C3), "infidelity": float(C1),
+            "penalty": float(C2), "integrated_infidelity": float(C3), "overlap": complex(g),
+            "grad": grad, "final_states": psi[N].T.copy()}

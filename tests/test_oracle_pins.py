@@ -51,6 +51,24 @@ def test_rabi_closed_form(seed):
     np.testing.assert_allclose(r["grad"][0], -dt * np.sin(2 * th), atol=1e-12)
 
 
+# ---- T1c: resonant Rabi, time-integrated infidelity C3 (App. A) -----------
+# psi_n = cos(th_n)|0> - i sin(th_n)|1>, th_n = dt sum_{j<=n} u_j, so
+# C3 = 1 - (1/N) sum_n sin^2(th_n) and dC3/du_k = -(dt/N) sum_{n>=k} sin(2 th_n)
+@pytest.mark.parametrize("seed", [0, 1])
+def test_rabi_time_integrated_closed_form(seed):
+    rng = np.random.default_rng(seed)
+    N, dt = 25, 0.1
+    u = rng.uniform(-2, 2, size=(1, N))
+    psi0 = np.array([[1, 0]], dtype=np.complex128)
+    tg = np.array([[0, 1]], dtype=np.complex128)
+    r = grape.cost_and_grad(np.zeros((2, 2)), [SX], u, dt, psi0, tg, w_fid=0.0, w_int=1.0)
+    th = dt * np.cumsum(u[0])
+    assert r["integrated_infidelity"] == pytest.approx(1 - np.mean(np.sin(th) ** 2), abs=1e-13)
+    assert r["cost"] == pytest.approx(r["integrated_infidelity"], abs=1e-15)
+    expect = -(dt / N) * np.cumsum(np.sin(2 * th)[::-1])[::-1]
+    np.testing.assert_allclose(r["grad"][0], expect, atol=1e-12)
+
+
 # ---- T1b: detuned Rabi, P1 = (a/Omega)^2 sin^2(Omega T), Omega^2 = a^2 + delta^2/4
 @pytest.mark.parametrize("a,delta", [(0.7, 0.4), (1.3, -2.0), (0.2, 3.0)])
 def test_detuned_rabi(a, delta):
@@ -92,7 +110,7 @@ def test_unitarity_and_norm():
 def test_finite_differences(frechet):
     rng = np.random.default_rng(4)
     H0, Hk, u, dt, psi0, tg, om = _small_problem(rng, d=6, K=2, N=5, S=2)
-    kw = dict(omega=om, w_fid=1.0, w_pen=0.7)
+    kw = dict(omega=om, w_fid=1.0, w_pen=0.7, w_int=0.6)
     r = grape.cost_and_grad(H0, Hk, u, dt, psi0, tg, frechet=frechet, **kw)
     errs = {}
     for h in (1e-3, 1e-4):
@@ -179,7 +197,7 @@ def test_commuting_closed_form():
 def test_costate_vs_brute_force(seed):
     rng = np.random.default_rng(seed)
     H0, Hk, u, dt, psi0, tg, om = _small_problem(rng, d=4, K=2, N=5, S=2)
-    kw = dict(omega=om, w_fid=0.8, w_pen=1.3)
+    kw = dict(omega=om, w_fid=0.8, w_pen=1.3, w_int=0.9)
     r = grape.cost_and_grad(H0, Hk, u, dt, psi0, tg, **kw)
     bf = grape.gradient_brute_force(H0, Hk, u, dt, psi0, tg, **kw)
     np.testing.assert_allclose(r["grad"], bf, atol=1e-13)
@@ -208,3 +226,30 @@ def test_sparse_and_dense_inputs_agree():
                             omega=om, w_pen=0.5)
     assert a["cost"] == b["cost"]
     np.testing.assert_array_equal(a["grad"], b["grad"])
+
+
+# ---- C3^g: with a full basis the time-integrated cost is App. A's gate form --
+def test_full_basis_time_integrated_gate_infidelity():
+    rng = np.random.default_rng(12)
+    d, K, N, dt = 4, 2, 6, 0.5
+    H0, Hk, u, _, _, _, _ = _small_problem(rng, d=d, K=K, N=N, S=1)
+    UT = np.linalg.qr(rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)))[0]
+    psi0 = np.eye(d, dtype=np.complex128)
+    tg = (UT @ psi0.T).T
+    r = grape.cost_and_grad(H0, Hk, u, dt, psi0, tg, w_fid=0.0, w_int=1.0)
+    UR = np.eye(d, dtype=np.complex128)
+    acc = 0.0
+    for n in range(N):
+        UR = grape.propagator(grape.hamiltonian(H0, Hk, u[:, n]), dt) @ UR
+        acc += abs(np.trace(UT.conj().T @ UR)) ** 2
+    assert r["integrated_infidelity"] == pytest.approx(1 - acc / (N * d * d), abs=1e-13)
+
+
+# ---- C3 with one step is C1 -----------------------------------------------
+def test_time_integrated_single_step_is_final_infidelity():
+    rng = np.random.default_rng(13)
+    H0, Hk, u, dt, psi0, tg, _ = _small_problem(rng, d=5, N=1, S=2)
+    a = grape.cost_and_grad(H0, Hk, u, dt, psi0, tg, w_fid=0.0, w_int=1.0)
+    b = grape.cost_and_grad(H0, Hk, u, dt, psi0, tg, w_fid=1.0)
+    assert a["cost"] == pytest.approx(b["cost"], abs=1e-14)
+    np.testing.assert_allclose(a["grad"], b["grad"], atol=1e-14)

@@ -86,7 +86,7 @@ def _schedule(p, tau=1e-12):
 def test_discrete_gradient_equals_fd_of_discrete_cost():
     p = make_config("cfg2", d_c=4, N=6)
     sched = _schedule(p)
-    kw = dict(omega=p.omega, w_fid=p.w_fid, w_pen=p.w_pen)
+    kw = dict(omega=p.omega, w_fid=p.w_fid, w_pen=p.w_pen, w_int=0.7)
     r = taylor.hg_discrete(p.H0, p.Hk, p.u, p.dt, p.psi0, p.targets, sched, **kw)
     h = 1e-5
     for (k, n) in [(0, 0), (1, 3), (3, 5), (2, 2)]:
@@ -100,8 +100,9 @@ def test_discrete_gradient_equals_fd_of_discrete_cost():
 def test_discrete_matches_exact_within_tau():
     p = make_config("cfg2", d_c=8, N=40)
     sched = _schedule(p)
-    kw = dict(omega=p.omega, w_fid=p.w_fid, w_pen=p.w_pen)
+    kw = dict(omega=p.omega, w_fid=p.w_fid, w_pen=p.w_pen, w_int=0.5)
     a = taylor.hg_discrete(p.H0, p.Hk, p.u, p.dt, p.psi0, p.targets, sched, **kw)
     b = grape.cost_and_grad(p.H0, p.Hk, p.u, p.dt, p.psi0, p.targets, **kw)
     assert a["cost"] == pytest.approx(b["cost"], rel=1e-11)
+    assert a["integrated_infidelity"] == pytest.approx(b["integrated_infidelity"], rel=1e-11)
     assert np.linalg.norm(a["grad"] - b["grad"]) <= 1e-10 * np.linalg.norm(b["grad"])
