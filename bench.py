@@ -37,10 +37,10 @@ def flops_per_term(nnz, nnz_ctrl, K):
     return fwd, bwd
 
 
-def run_precision(hg, prob, u, psi0, tg, p, dtype, steps, warmup):
+def run_precision(hg, prob, u, psi0, tg, p, dtype, steps, warmup, w_int=0.0):
     import numpy as np
     import torch
-    kw = dict(w_fid=p.w_fid, w_pen=p.w_pen, tau=p.tau, dtype=dtype, timing=True)
+    kw = dict(w_fid=p.w_fid, w_pen=p.w_pen, w_int=w_int, tau=p.tau, dtype=dtype, timing=True)
     for w in range(warmup):
         hg.evaluate(prob, u, psi0, tg, p.dt, **kw)
         log(f"  warmup {w + 1}/{warmup} {dtype} done")
@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--serve-inflight", type=int, default=32)
     ap.add_argument("--serve-qps", type=float, default=4.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-integrated", action="store_true",
+                    help="skip the leg with the time-integrated infidelity term")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for the "
                          "FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -240,6 +242,15 @@ def main():
         line["c64_over_c128"] = main_r["evals_per_s"] / c["evals_per_s"]
     line["kernel_ms"] = {d: {"forward": out[d]["ms_forward"], "backward": out[d]["ms_backward"]}
                          for d in out}
+    if not args.no_integrated:
+        # the same workload with the time-integrated infidelity C3 added (App. A)
+        log("[bench] c64 with the time-integrated infidelity term (w_int = 1)")
+        ri = run_precision(hg, prob, u, psi0, tg, p, "c64", args.steps, args.warmup, w_int=1.0)
+        line["with_integrated_infidelity"] = {
+            "value": B / (ri["ms_per_step"] * 1e-3), "unit": "evals/s", "dtype": "c64",
+            "ms_forward": ri["ms_forward"], "ms_backward": ri["ms_backward"],
+            "slowdown": ri["ms_per_step"] / main_r["ms_per_step"]}
+        log(f"[bench] c64 + C3: {line['with_integrated_infidelity']['value']:.3f} evals/s")
     if not args.no_serving:
         log(f"[bench] serving stream: {args.serve_requests} requests, {args.serve_inflight} slots")
         budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)

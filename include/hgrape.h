@@ -130,6 +130,10 @@ typedef struct {
   const double* psi0;        /* device [B][S][dim] complex128, each column normalised */
   const double* targets;     /* device [B][S][dim] complex128 target states phi_T^h */
   double w_fid, w_pen;       /* cost weights alpha_nu (Sec. II); w_pen ignored without Omega */
+  double w_int;              /* weight of the time-integrated infidelity
+                                C3 = 1 - (1/N) sum_{n=1..N} |g_n|^2, g_n the overlap
+                                (1/S) sum_h <phi_T^h|psi_n^h> after step n (App. A:
+                                C3^st for S = 1, C3^g for a full basis); 0 = off */
   double tau;                /* per-step tolerance of the Taylor action (Sec. III.B) */
   hg_dtype dtype;            /* arithmetic of the state products (norms, planner,
                                 overlaps and reductions are FP64 in both) */
@@ -146,9 +150,10 @@ typedef struct {
 #define HG_FLAG_TIMING 1
 
 typedef struct {
-  double cost;               /* w_fid * infidelity + w_pen * penalty */
+  double cost;               /* w_fid C1 + w_pen C2 + w_int C3 */
   double infidelity;         /* C1 = 1 - |g|^2 */
   double penalty;            /* C2 */
+  double integrated_infidelity;  /* C3 (computed when w_int != 0, else 0) */
   double overlap_re, overlap_im;  /* g */
   int64_t sum_mu;            /* sum over steps of m_n s_n */
   double max_theta;          /* max_n ||A_n||_1 */

@@ -55,13 +55,14 @@ class hg_eval_desc(C.Structure):
     _fields_ = [("n_steps", C.c_int32), ("n_batch", C.c_int32), ("dt", C.c_double),
                 ("u", C.c_void_p), ("n_states", C.c_int32), ("psi0", C.c_void_p),
                 ("targets", C.c_void_p), ("w_fid", C.c_double), ("w_pen", C.c_double),
-                ("tau", C.c_double), ("dtype", C.c_int), ("mode", C.c_int),
+                ("w_int", C.c_double), ("tau", C.c_double), ("dtype", C.c_int), ("mode", C.c_int),
                 ("ckpt_every", C.c_int32), ("renorm_every", C.c_int32),
                 ("schedule", C.POINTER(C.c_int32)), ("flags", C.c_int32)]
 
 
 class hg_result(C.Structure):
     _fields_ = [("cost", C.c_double), ("infidelity", C.c_double), ("penalty", C.c_double),
+                ("integrated_infidelity", C.c_double),
                 ("overlap_re", C.c_double), ("overlap_im", C.c_double), ("sum_mu", C.c_int64),
                 ("max_theta", C.c_double), ("max_bound", C.c_double), ("drift", C.c_double),
                 ("ms_forward", C.c_double), ("ms_backward", C.c_double)]

@@ -93,6 +93,7 @@ class EvalResult:
     grad: object            # torch tensor (B, K, N) float64 on the device, or None
     ms_forward: float = 0.0   # kernel times of the whole batch (timing=True)
     ms_backward: float = 0.0
+    integrated_infidelity: Optional[np.ndarray] = None  # (B,) C3 (w_int != 0)
 
 
 def _ptr(t) -> int:
@@ -100,7 +101,8 @@ def _ptr(t) -> int:
 
 
 def make_desc(n_steps, n_batch, dt, u, n_states, psi0, targets, w_fid, w_pen, tau, dtype,
-              renorm_every, schedule=None, mode=L.HG_MODE_RECONSTRUCT, ckpt_every=0, flags=0):
+              renorm_every, schedule=None, mode=L.HG_MODE_RECONSTRUCT, ckpt_every=0, flags=0,
+              w_int=0.0):
     d = L.hg_eval_desc()
     d.n_steps = n_steps
     d.n_batch = n_batch
@@ -111,6 +113,7 @@ def make_desc(n_steps, n_batch, dt, u, n_states, psi0, targets, w_fid, w_pen, ta
     d.targets = targets
     d.w_fid = w_fid
     d.w_pen = w_pen
+    d.w_int = w_int
     d.tau = tau
     d.dtype = dtype
     d.mode = mode
@@ -122,7 +125,7 @@ def make_desc(n_steps, n_batch, dt, u, n_states, psi0, targets, w_fid, w_pen, ta
 
 
 def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.0,
-             w_pen: float = 0.0, tau: float = 1e-12, dtype: str = "c128",
+             w_pen: float = 0.0, w_int: float = 0.0, tau: float = 1e-12, dtype: str = "c128",
              renorm_every: Optional[int] = None, schedule: Optional[np.ndarray] = None,
              want_grad: bool = True, timing: bool = False, mode: str = "reconstruct",
              ckpt_every: int = 0, stream=None) -> EvalResult:
@@ -135,6 +138,7 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
     schedule optional host int array (2, B, N) or (2, N) of frozen (m, s)
     mode     "reconstruct" (HG inverse propagation) or "checkpoint" (psi stored
              every ckpt_every steps, segments re-propagated in the backward sweep)
+    w_int    weight of the time-integrated infidelity C3 (0 = off)
     """
     torch = _torch()
     if u.dim() == 2:
@@ -172,7 +176,8 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
     mcode = {"reconstruct": L.HG_MODE_RECONSTRUCT, "checkpoint": L.HG_MODE_CHECKPOINT}[mode]
     desc = make_desc(N, B, dt, _ptr(u) if K > 0 else None, S, _ptr(psi0), _ptr(targets),
                      w_fid, w_pen, tau, code, renorm_every, sched_p, mode=mcode,
-                     ckpt_every=ckpt_every, flags=L.HG_FLAG_TIMING if timing else 0)
+                     ckpt_every=ckpt_every, flags=L.HG_FLAG_TIMING if timing else 0,
+                     w_int=w_int)
     grad = torch.empty((B, K, N), dtype=torch.float64, device=u.device) if want_grad and K > 0 else None
     res = (L.hg_result * B)()
     st = stream if stream is not None else torch.cuda.current_stream(u.device).cuda_stream
@@ -186,7 +191,8 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
         max_theta=np.array([r.max_theta for r in res]),
         max_bound=np.array([r.max_bound for r in res]),
         drift=np.array([r.drift for r in res]),
-        grad=grad, ms_forward=res[0].ms_forward, ms_backward=res[0].ms_backward)
+        grad=grad, ms_forward=res[0].ms_forward, ms_backward=res[0].ms_backward,
+        integrated_infidelity=np.array([r.integrated_infidelity for r in res]))
 
 
 def step_norms(problem: Problem, u, dt: float, stream=None):

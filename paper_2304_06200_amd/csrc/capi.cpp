@@ -316,10 +316,11 @@ hg_status hg_step_norms(hg_problem* p, const double* u, int32_t n_batch, int32_t
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Workspace {
-  size_t theta, pnorm, sched, psiN, cold, ckpt, segbuf, ovl, pen, gradp, drift, res, total;
+  size_t theta, pnorm, sched, psiN, cold, ckpt, segbuf, ovl, ovt, gt, pen, gradp, drift, res, total;
 };
 
-static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128, int ckpt_every) {
+static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128, int ckpt_every,
+                        bool integrated) {
   const size_t cs = c128 ? 16 : 8;
   const size_t d = (size_t)p->dim, K = (size_t)p->n_ctrl;
   Workspace w{};
@@ -339,6 +340,8 @@ static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128, int
   w.ckpt = take((size_t)B * S * nseg * d * cs);
   w.segbuf = take((size_t)B * S * C * d * cs);
   w.ovl = take((size_t)B * S * 16);
+  w.ovt = take(integrated ? (size_t)B * S * N * 16 : 0);
+  w.gt = take(integrated ? (size_t)B * N * 16 : 0);
   w.pen = take((size_t)B * S * 8);
   w.gradp = take((size_t)B * S * std::max<size_t>(K, 1) * N * 8);
   w.drift = take((size_t)B * S * 8);
@@ -353,7 +356,8 @@ static hg_status check_desc(const hg_problem* p, const hg_eval_desc* d) {
   if (d->n_batch < 1) return fail(HG_ERR_INVALID_ARG, "n_batch must be >= 1");
   if (d->n_states < 1) return fail(HG_ERR_INVALID_ARG, "n_states must be >= 1");
   if (!std::isfinite(d->dt) || !(d->dt > 0.0)) return fail(HG_ERR_INVALID_ARG, "dt must be finite and > 0");
-  if (!std::isfinite(d->w_fid) || !std::isfinite(d->w_pen)) return fail(HG_ERR_NONFINITE, "weights");
+  if (!std::isfinite(d->w_fid) || !std::isfinite(d->w_pen) || !std::isfinite(d->w_int))
+    return fail(HG_ERR_NONFINITE, "weights");
   if (!(d->tau > 0.0) || !std::isfinite(d->tau)) return fail(HG_ERR_INVALID_ARG, "tau must be > 0");
   if (d->dtype != HG_C64 && d->dtype != HG_C128) return fail(HG_ERR_INVALID_ARG, "dtype");
   if (d->mode != HG_MODE_RECONSTRUCT && d->mode != HG_MODE_CHECKPOINT)
@@ -371,7 +375,8 @@ hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* d, size_t* 
   if (st != HG_OK) return st;
   if (!bytes) return fail(HG_ERR_INVALID_ARG, "bytes is NULL");
   *bytes = layout(p, d->n_batch, d->n_steps, d->n_states, d->dtype == HG_C128,
-                  d->mode == HG_MODE_CHECKPOINT ? d->ckpt_every : 0).total;
+                  d->mode == HG_MODE_CHECKPOINT ? d->ckpt_every : 0,
+                  d->w_int != 0.0).total;
   return HG_OK;
 }
 
@@ -394,7 +399,7 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, doub
   sh.n_batch = B;
 
   const int ck = d->mode == HG_MODE_CHECKPOINT ? std::min(d->ckpt_every, N) : 0;
-  const Workspace w = layout(p, B, N, S, c128, ck);
+  const Workspace w = layout(p, B, N, S, c128, ck, d->w_int != 0.0);
   char* ws = nullptr;
   if (hipMallocAsync((void**)&ws, w.total, hs) != hipSuccess)
     return fail(HG_ERR_OUT_OF_MEMORY, "workspace of " + std::to_string(w.total) + " bytes");
@@ -480,6 +485,8 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, doub
   bf.ckpt = ck > 0 ? ws + w.ckpt : nullptr;
   bf.segbuf = ck > 0 ? ws + w.segbuf : nullptr;
   bf.ovl = (double*)(ws + w.ovl);
+  bf.ovt = d->w_int != 0.0 ? (double*)(ws + w.ovt) : nullptr;
+  bf.gt = d->w_int != 0.0 ? (double*)(ws + w.gt) : nullptr;
   bf.pen = (double*)(ws + w.pen);
   bf.gradp = (double*)(ws + w.gradp);
   bf.drift = (double*)(ws + w.drift);
@@ -495,7 +502,7 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, doub
   } evguard{bf.ev};
   if (d->flags & HG_FLAG_TIMING)
     for (int i = 0; i < 3; ++i) HG_HIP(hipEventCreate(&bf.ev[i]));
-  SweepParams sp{d->dt, d->w_fid, d->w_pen, d->renorm_every, ck};
+  SweepParams sp{d->dt, d->w_fid, d->w_pen, d->w_int, d->renorm_every, ck};
   HG_HIP(launch_sweep(p->ops, sh, bf, sp, hs));
   HG_HIP(hipMemcpyAsync(h_res, bf.res, (size_t)B * 8 * 8, hipMemcpyDeviceToHost, hs));
   HG_HIP(hipMemcpyAsync(h_drift, bf.drift, (size_t)B * S * 8, hipMemcpyDeviceToHost, hs));
@@ -511,6 +518,7 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, doub
     r.cost = h_res[b * 8 + 0];
     r.infidelity = h_res[b * 8 + 1];
     r.penalty = h_res[b * 8 + 2];
+    r.integrated_infidelity = h_res[b * 8 + 5];
     r.overlap_re = h_res[b * 8 + 3];
     r.overlap_im = h_res[b * 8 + 4];
     int64_t mu = 0;

@@ -88,6 +88,8 @@ struct SweepBuffers {
   void* ckpt;                      // checkpoint variant: [B][S][ceil(N/C)][dim], else null
   void* segbuf;                    // checkpoint variant: [B][S][C][dim], else null
   double* ovl;                     // [B][S][2]
+  double* ovt;                     // [B][S][N][2] overlaps after every step, or null (w_int == 0)
+  double* gt;                      // [B][N][2] their averages over the S states (with ovt)
   double* pen;                     // [B][S]
   double* gradp;                   // [B][S][K][N]
   double* drift;                   // [B][S]
@@ -96,7 +98,7 @@ struct SweepBuffers {
   hipEvent_t ev[3];                // optional: before forward, between, after backward
 };
 struct SweepParams {
-  double dt, w_fid, w_pen;
+  double dt, w_fid, w_pen, w_int;
   int renorm_every;
   int ckpt_every;  // 0: reconstruction; > 0: checkpoint every C steps
 };

@@ -51,11 +51,13 @@ struct SweepArgs {
   void* ckpt;            // [B][S][ceil(N/C)][d] checkpoints psi_0, psi_C, ... (checkpoint variant)
   void* segbuf;          // [B][S][C][d] states of the segment being swept back
   double* ovl;           // [B][S][2]
+  double* ovt;           // [B][S][N][2] overlap after each step, or null (no C3 term)
+  double* gt;            // [B][N][2] g_n = (1/S) sum_h ovt (filled between the sweeps)
   double* pen;           // [B][S]
   double* gradp;         // [B][S][K][N]
   double* drift;         // [B][S]
   double* res;           // [B][8]
-  double dt, w_fid, w_pen;
+  double dt, w_fid, w_pen, w_int;
 };
 
 template <typename R>
@@ -569,6 +571,23 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
         if (ok[r]) ck[(size_t)((n + 1) / CK) * d + row[r]] = acc[r][0];
+    if (a.ovt) {
+      // <phi_T|psi_{n+1}> of this column for the time-integrated infidelity
+      double o[2] = {0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (ok[r]) {
+          const double2 t = a.tgt[col0 + row[r]];
+          const double pr = acc[r][0].re, pi = acc[r][0].im;
+          o[0] += t.x * pr + t.y * pi;
+          o[1] += t.x * pi - t.y * pr;
+        }
+      block_sum<2>(o, red);
+      if (tid == 0) {
+        a.ovt[(((size_t)b * a.S + h) * a.N + n) * 2 + 0] = o[0];
+        a.ovt[(((size_t)b * a.S + h) * a.N + n) * 2 + 1] = o[1];
+      }
+    }
   }
 
   C* psiN = reinterpret_cast<C*>(a.psiN);
@@ -662,16 +681,22 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   gre /= (double)S;
   gim /= (double)S;
   const double cpen = a.omega ? a.w_pen / ((double)N * S) : 0.0;
+  // time-integrated infidelity: C3 (written by k_integrated) and the source
+  // -(w_int/(N S)) g_n phi_T of every state psi_n, n = N..1 (App. A, Phi_T,n)
+  const double cint = a.ovt ? a.w_int / ((double)N * S) : 0.0;
   if (h == 0 && tid == 0) {
     const double C1 = 1.0 - (gre * gre + gim * gim);
     const double C2 = a.omega ? ptot / ((double)N * S) : 0.0;
-    a.res[(size_t)b * 8 + 0] = a.w_fid * C1 + (a.omega ? a.w_pen * C2 : 0.0);
+    const double C3 = a.ovt ? a.res[(size_t)b * 8 + 5] : 0.0;
+    a.res[(size_t)b * 8 + 0] =
+        a.w_fid * C1 + (a.omega ? a.w_pen * C2 : 0.0) + (a.ovt ? a.w_int * C3 : 0.0);
     a.res[(size_t)b * 8 + 1] = C1;
     a.res[(size_t)b * 8 + 2] = C2;
     a.res[(size_t)b * 8 + 3] = gre;
     a.res[(size_t)b * 8 + 4] = gim;
+    a.res[(size_t)b * 8 + 5] = C3;
   }
-  const double fr = -a.w_fid * gre / S, fi = -a.w_fid * gim / S;
+  const double fr = -(a.w_fid / S + cint) * gre, fi = -(a.w_fid / S + cint) * gim;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const bool shared = tailw && r == RPT - 1;
@@ -822,16 +847,28 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
           a.gradp[(((size_t)b * S + h) * K + g0 + v) * N + n] = 2.0 * gv[v];
     }
 
+    double sgr = 0.0, sgi = 0.0;  // -(w_int/(N S)) g_n for the source of psi_n
+    if (a.ovt && n >= 1) {
+      sgr = -cint * a.gt[((size_t)b * N + n - 1) * 2 + 0];
+      sgi = -cint * a.gt[((size_t)b * N + n - 1) * 2 + 1];
+    }
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int i = opaque(row[r]);
       const C ps = ok[r] ? c_psi[i] : C{(R)0, (R)0};
       pl[r][0] = own_psi[r] ? ps : C{(R)0, (R)0};
       pl[r][1] = own_lam[r] ? c_lam[i] : C{(R)0, (R)0};
-      if (n >= 1 && a.omega && own_lam[r]) {
-        const double w = cpen * a.omega[i];
-        pl[r][1].re = (R)((double)pl[r][1].re + w * (double)ps.re);
-        pl[r][1].im = (R)((double)pl[r][1].im + w * (double)ps.im);
+      if (n >= 1 && own_lam[r] && (a.omega || a.ovt)) {
+        const double w = a.omega ? cpen * a.omega[i] : 0.0;
+        double lr = (double)pl[r][1].re + w * (double)ps.re;
+        double li = (double)pl[r][1].im + w * (double)ps.im;
+        if (a.ovt) {
+          const double2 t = a.tgt[col0 + i];
+          lr += sgr * t.x - sgi * t.y;
+          li += sgr * t.y + sgi * t.x;
+        }
+        pl[r][1].re = (R)lr;
+        pl[r][1].im = (R)li;
       }
     }
   }

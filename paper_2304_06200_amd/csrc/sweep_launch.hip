@@ -81,6 +81,40 @@ __global__ void __launch_bounds__(256) k_reduce_grad(const double* gradp, double
   grad[idx] = s;
 }
 
+// Time-integrated infidelity (App. A): g_n = (1/S) sum_h <phi_T^h|psi_n^h> for
+// every step (h ascending) and C3 = 1 - (1/N) sum_n |g_n|^2 per evaluation
+// (fixed-order block reduction), written to res[b][5].  One block per b.
+__global__ void __launch_bounds__(256) k_integrated(const double* ovt, double* gt, double* res,
+                                                    int S, int N) {
+  __shared__ double red[256];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  double acc = 0.0;
+  for (int n = tid; n < N; n += 256) {
+    double gr = 0.0, gi = 0.0;
+    for (int h = 0; h < S; ++h) {
+      gr += ovt[(((size_t)b * S + h) * N + n) * 2 + 0];
+      gi += ovt[(((size_t)b * S + h) * N + n) * 2 + 1];
+    }
+    gr /= S;
+    gi /= S;
+    gt[((size_t)b * N + n) * 2 + 0] = gr;
+    gt[((size_t)b * N + n) * 2 + 1] = gi;
+    acc += gr * gr + gi * gi;
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) res[(size_t)b * 8 + 5] = 1.0 - red[0] / N;
+}
+
+hipError_t launch_integrated(const SweepArgs& a, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_integrated, dim3(nb), dim3(256), 0, st, a.ovt, a.gt, a.res, a.S, a.N);
+  return hipGetLastError();
+}
+
 hipError_t launch_step_norms(const DevOps& ops, int dim, int K, const double* u, int nb, int N,
                              double dt, double* theta, hipStream_t st) {
   hipLaunchKernelGGL(k_step_norms, dim3(N, nb), dim3(256), 0, st, ops.vals, ops.W, dim, K, u, N,
@@ -216,6 +250,8 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
   a.ckpt = bf.ckpt;
   a.segbuf = bf.segbuf;
   a.ovl = bf.ovl;
+  a.ovt = bf.ovt;
+  a.gt = bf.gt;
   a.pen = bf.pen;
   a.gradp = bf.gradp;
   a.drift = bf.drift;
@@ -223,6 +259,7 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
   a.dt = p.dt;
   a.w_fid = p.w_fid;
   a.w_pen = p.w_pen;
+  a.w_int = p.w_int;
   hipError_t e;
   switch (width_template(ops.W)) {
     case 3: e = run_width_3(a, sh, st, bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr); break;

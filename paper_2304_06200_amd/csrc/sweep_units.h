@@ -13,6 +13,8 @@ hipError_t run_width_5(const SweepArgs& a, const SweepShape& sh, hipStream_t st,
 hipError_t run_width_9(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
 hipError_t run_width_13(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
 
+hipError_t launch_integrated(const SweepArgs& a, int nb, hipStream_t st);
+
 template <typename R, int RPT, int W, int WK, int G>
 hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream_t st,
                              hipEvent_t* ev) {
@@ -39,6 +41,7 @@ hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream
   hipLaunchKernelGGL(fk, grid, fblock, sh.lds_fwd, st, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (a.ovt && (e = launch_integrated(a, sh.n_batch, st)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
   hipLaunchKernelGGL(bk, grid, block, sh.lds_bwd, st, a);
   e = hipGetLastError();

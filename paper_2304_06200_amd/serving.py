@@ -28,7 +28,7 @@ class Server:
         self.handle = L.hg_server_create(ctx.handle, int(hbm_budget_bytes), int(max_inflight))
 
     def submit(self, problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.0,
-               w_pen: float = 0.0, tau: float = 1e-12, dtype: str = "c64",
+               w_pen: float = 0.0, w_int: float = 0.0, tau: float = 1e-12, dtype: str = "c64",
                renorm_every: Optional[int] = None, mode: str = "reconstruct",
                ckpt_every: int = 0) -> Handle:
         """u: float64 device tensor (K, N) or (B, K, N); psi0, targets: complex128
@@ -51,7 +51,7 @@ class Server:
         mcode = {"reconstruct": L.HG_MODE_RECONSTRUCT, "checkpoint": L.HG_MODE_CHECKPOINT}[mode]
         desc = make_desc(N, B, dt, int(u.data_ptr()) if K > 0 else None, S, int(psi0.data_ptr()),
                          int(targets.data_ptr()), w_fid, w_pen, tau, code, renorm_every, None,
-                         mode=mcode, ckpt_every=ckpt_every)
+                         mode=mcode, ckpt_every=ckpt_every, w_int=w_int)
         grad = torch.empty((B, K, N), dtype=torch.float64, device=u.device) if K > 0 else None
         res = (L.hg_result * B)()
         rid = L.hg_server_submit(self.handle, problem.handle, desc, res,
@@ -76,7 +76,8 @@ class Server:
             overlap=np.array([complex(x.overlap_re, x.overlap_im) for x in r]),
             sum_mu=np.array([x.sum_mu for x in r], dtype=np.int64),
             max_theta=np.array([x.max_theta for x in r]), max_bound=np.array([x.max_bound for x in r]),
-            drift=np.array([x.drift for x in r]), grad=h.grad)
+            drift=np.array([x.drift for x in r]), grad=h.grad,
+            integrated_infidelity=np.array([x.integrated_infidelity for x in r]))
         return res, lat, q
 
     def info(self):

@@ -46,8 +46,9 @@ def run(p, dtype="c128", prob=None, schedule=None, batch_u=None, **kw):
     import paper_2304_06200_amd as hg
     prob = prob or make_problem(p)
     u, psi0, tg = device_inputs(p, batch_u)
-    return hg.evaluate(prob, u, psi0, tg, p.dt, w_fid=p.w_fid, w_pen=p.w_pen,
-                       tau=kw.pop("tau", p.tau), dtype=dtype, schedule=schedule, **kw)
+    return hg.evaluate(prob, u, psi0, tg, p.dt, w_fid=kw.pop("w_fid", p.w_fid),
+                       w_pen=kw.pop("w_pen", p.w_pen), tau=kw.pop("tau", p.tau), dtype=dtype,
+                       schedule=schedule, **kw)
 
 
 def rel(a, b):
