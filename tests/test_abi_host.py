@@ -108,3 +108,36 @@ def test_planner_exact_at_thresholds():
     for t, sig in pts:
         mm, ss = _lib.hg_plan(np.array([t]), sig, 1e-12, 2.0 ** -53)
         assert (int(mm[0]), int(ss[0])) == oplan.select(float(t), sig, 1e-12), (t, sig)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes mirrors of hg_eval_desc, hg_result and hg_csr have the field
+    offsets and sizes that a C compiler gives the header's structs."""
+    import shutil
+    import subprocess
+    import ctypes as C
+    from paper_2304_06200_amd import _lib as L
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"hg_eval_desc": L.hg_eval_desc, "hg_result": L.hg_result, "hg_csr": L.hg_csr}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hgrape.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
