@@ -167,6 +167,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-integrated", action="store_true",
                     help="skip the leg with the time-integrated infidelity term")
+    ap.add_argument("--no-gate", action="store_true",
+                    help="skip the full-basis gate leg (three coupled transmons)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for the "
                          "FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -242,6 +244,20 @@ def main():
         line["c64_over_c128"] = main_r["evals_per_s"] / c["evals_per_s"]
     line["kernel_ms"] = {d: {"forward": out[d]["ms_forward"], "backward": out[d]["ms_backward"]}
                          for d in out}
+    # device memory of one evaluation (Table I): HG reconstruction keeps no state
+    # history; checkpointing every step stores it (the stored-history comparator)
+    from paper_2304_06200_amd import _lib as L
+    from paper_2304_06200_amd.api import make_desc
+
+    def footprint(mode, C):
+        desc = make_desc(p.n_steps, 1, p.dt, 1, p.n_states, 1, 1, p.w_fid, p.w_pen, p.tau,
+                         L.HG_C64, 1, None, mode=mode, ckpt_every=C)
+        return int(L.hg_eval_footprint(prob.handle, desc))
+    line["memory_per_eval_bytes"] = {
+        "reconstruct": footprint(L.HG_MODE_RECONSTRUCT, 0),
+        "checkpoint_every_100": footprint(L.HG_MODE_CHECKPOINT, 100),
+        "stored_history": footprint(L.HG_MODE_CHECKPOINT, 1),
+        "note": "c64 workspace of one cfg3 evaluation; stored_history = every psi_n kept"}
     if not args.no_integrated:
         # the same workload with the time-integrated infidelity C3 added (App. A)
         log("[bench] c64 with the time-integrated infidelity term (w_int = 1)")
@@ -251,6 +267,23 @@ def main():
             "ms_forward": ri["ms_forward"], "ms_backward": ri["ms_backward"],
             "slowdown": ri["ms_per_step"] / main_r["ms_per_step"]}
         log(f"[bench] c64 + C3: {line['with_integrated_infidelity']['value']:.3f} evals/s")
+    if not args.no_gate:
+        # the paper's second workload: a full-basis gate on three coupled transmons
+        # (8 levels each, d = S = 512), one step as in its benchmark
+        pg = make_config("gate3", d_t=8)
+        log(f"[bench] gate3 d={pg.dim} S={pg.n_states} N={pg.n_steps}")
+        probg = hg.Problem(ctx, pg.H0, pg.Hk, pg.omega)
+        ug = torch.tensor(pg.u, dtype=torch.float64, device="cuda")
+        pg0 = torch.tensor(pg.psi0, dtype=torch.complex128, device="cuda")
+        tgg = torch.tensor(pg.targets, dtype=torch.complex128, device="cuda")
+        line["gate"] = {"workload": "gate3: three coupled transmons (8 levels each), d = 512, "
+                                    "full basis S = 512, simultaneous Hadamards, N = 1, dt = 0.25 ns"}
+        for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
+            rg = run_precision(hg, probg, ug, pg0, tgg, pg, dtype, max(args.steps, 3), args.warmup)
+            line["gate"][dtype] = {"value": 1.0 / (rg["ms_per_step"] * 1e-3), "unit": "evals/s",
+                                   "ms_per_step": rg["ms_per_step"],
+                                   "sum_mu": int(np.sum(rg["sum_mu"]))}
+            log(f"[bench] gate3 {dtype}: {line['gate'][dtype]['value']:.2f} evals/s")
     if not args.no_serving:
         log(f"[bench] serving stream: {args.serve_requests} requests, {args.serve_inflight} slots")
         budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)

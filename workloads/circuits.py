@@ -68,6 +68,23 @@ def transmon_cavity_system(d_t: int, d_c: int, alpha: float, chi: float):
     return H0, [bx, by, cx, cy], dims
 
 
+def three_transmon_chain(d_t: int, alpha: float, g: float):
+    """Three resonantly driven transmons (d_t levels each) with nearest-neighbour
+    exchange, in the rotating frame (Sec. IV.B, eq. gateH):
+
+    H0 = sum_nu (alpha/2) n_nu (n_nu - 1) + g (b1 b2^dag + b2 b3^dag + h.c.)
+    Drives: b_nu + b_nu^dag for nu = 1, 2, 3 (three controls).
+    """
+    dims = (d_t, d_t, d_t)
+    b = [embed(destroy(d_t), i, dims) for i in range(3)]
+    n = [embed(number(d_t), i, dims) for i in range(3)]
+    ident = sp.identity(d_t ** 3, dtype=np.complex128, format="csr")
+    H0 = sum(0.5 * alpha * (n[i] @ (n[i] - ident)) for i in range(3))
+    hop = b[0] @ b[1].conj().T + b[1] @ b[2].conj().T
+    H0 = _clean(H0 + g * (hop + hop.conj().T))
+    return H0, [_clean(bi + bi.conj().T) for bi in b], dims
+
+
 def two_transmon_cavity_system(d_t: int, d_c: int, alpha: float, chi: float, g: float):
     """Two transmons (d_t levels each) sharing a cavity (d_c levels).
 

@@ -21,7 +21,8 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-from .circuits import (Problem, basis_state, haar_unitary, transmon_cavity_system,
+from .circuits import (Problem, basis_state, haar_unitary, three_transmon_chain,
+                       transmon_cavity_system,
                        two_transmon_cavity_system)
 
 TWO_PI = 2.0 * np.pi
@@ -105,6 +106,32 @@ def cfg5(N: int = 5000, seed: int = 5, d_c: int = 1024) -> Problem:
                    _top_level_projector(dims), w_fid=1.0, w_pen=1.0, dims=dims)
 
 
+def gate3(d_t: int = 4, N: int = 1, dt: float = 0.25, seed: int = 6,
+          random_amps: bool = False) -> Problem:
+    """Full-basis gate on three coupled transmons (Sec. IV.B, eq. gateH):
+    alpha/2pi = -0.225 GHz, g/2pi = 0.1 GHz, drive amplitudes a/2pi = 0.1 GHz
+    (constant, as in the paper's single-step benchmark, or seeded uniform in
+    +-0.1 GHz with random_amps).  S = d initial states (the full product basis);
+    target U_T = simultaneous Hadamards, each acting on levels {0, 1} of its
+    transmon and as the identity on the levels above (reading for d_t > 2).
+    dt = 0.25 ns (not stated for this benchmark): ||A||_1 grows as d_t^2 through
+    the anharmonicity, and at d_t = 8 a longer step puts tau = 1e-12 below the
+    floor of the App. C bound."""
+    H0, Hk, dims = three_transmon_chain(d_t, -TWO_PI * 0.225, TWO_PI * 0.1)
+    d = d_t ** 3
+    if random_amps:
+        u = TWO_PI * 0.1 * np.random.default_rng(seed).uniform(-1.0, 1.0, (3, N))
+    else:
+        u = np.full((3, N), TWO_PI * 0.1)
+    h1 = np.eye(d_t, dtype=np.complex128)
+    h1[:2, :2] = np.array([[1, 1], [1, -1]]) / np.sqrt(2)
+    UT = np.kron(np.kron(h1, h1), h1)
+    psi0 = np.eye(d, dtype=np.complex128)
+    targets = (UT @ psi0.T).T.copy()
+    return Problem(f"gate3_t{d_t}", H0, Hk, dt, u, psi0, targets, None, w_fid=1.0, w_pen=0.0,
+                   dims=dims)
+
+
 def serving_request(i: int, d_c: int, N: int, S: int) -> Problem:
     """One request of the serving stream: transmon(3) x cavity(d_c), dt = 1 ns."""
     d_t = 3
@@ -134,7 +161,7 @@ def serving_stream(n_req: int = 256, seed: int = 4, d_c_max: int = 700,
     return out
 
 
-CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg5": cfg5}
+CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg5": cfg5, "gate3": gate3}
 
 
 def make_config(name: str, **kw) -> Problem:
