@@ -13,9 +13,9 @@ the cavity index running fastest.  Units: rad/ns for energies, ns for time,
 hbar = 1.
 """
 from .circuits import (destroy, number, embed, transmon_cavity_system,
-                       two_transmon_cavity_system, haar_unitary, Problem)
+                       two_transmon_cavity_system, three_transmon_chain, haar_unitary, Problem)
 from .configs import CONFIGS, make_config, serving_stream, problem_summary
 
 __all__ = ["destroy", "number", "embed", "transmon_cavity_system",
-           "two_transmon_cavity_system", "haar_unitary", "Problem",
+           "two_transmon_cavity_system", "three_transmon_chain", "haar_unitary", "Problem",
            "CONFIGS", "make_config", "serving_stream", "problem_summary"]
