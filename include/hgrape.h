@@ -167,8 +167,10 @@ typedef struct {
  * grad: device [B][n_ctrl][N] FP64 (may be NULL for cost only).  Work is
  * enqueued on `stream`; the call returns after the stream has finished it
  * (the planner needs the norms on the host mid-way), so results and grad
- * are valid on return.  Errors: INVALID_ARG, NONFINITE, TOLERANCE_UNREACHABLE,
- * UNSUPPORTED, OUT_OF_MEMORY, DEVICE. */
+ * are valid on return.  One workgroup holds one state column's term vectors
+ * in LDS: UNSUPPORTED when they do not fit (e.g. complex128 above 2048 rows).
+ * Errors: INVALID_ARG, NONFINITE, TOLERANCE_UNREACHABLE, UNSUPPORTED,
+ * OUT_OF_MEMORY, DEVICE. */
 hg_status hg_eval(hg_problem* p, const hg_eval_desc* desc, hg_result* results,
                   double* grad, void* stream);
 
