@@ -52,6 +52,7 @@ struct hg_problem {
   int64_t nnz = 0;                 // stored union non-zeros (structural)
   std::vector<int64_t> nnz_ctrl;   // structural non-zeros of each H_k
   hg::DevOps ops;
+  ~hg_problem();                   // frees the device arrays (also on a failed creation)
 };
 
 namespace hg {

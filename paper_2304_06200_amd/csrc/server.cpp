@@ -82,8 +82,18 @@ void worker_loop(hg_server* sv, int w) {
       r->t_start = Clock::now();
     }
     if (!r->schedule.empty()) r->desc.schedule = r->schedule.data();
-    const hg_status st = hg_eval(r->p, &r->desc, r->results, r->grad, sv->streams[w]);
-    const std::string err = st == HG_OK ? std::string() : std::string(hg_last_error());
+    hg_status st;
+    std::string err;
+    try {  // no exception may end a worker thread (or cross the C ABI)
+      st = hg_eval(r->p, &r->desc, r->results, r->grad, sv->streams[w]);
+      if (st != HG_OK) err = hg_last_error();
+    } catch (const std::bad_alloc&) {
+      st = HG_ERR_OUT_OF_MEMORY;
+      err = "host allocation failed";
+    } catch (...) {
+      st = HG_ERR_DEVICE;
+      err = "unexpected exception in the evaluation";
+    }
     {
       std::lock_guard<std::mutex> lk(sv->mu);
       sv->in_use -= r->bytes;
@@ -115,6 +125,7 @@ hg_status hg_server_create(hg_ctx* ctx, size_t hbm_budget_bytes, int32_t max_inf
     hg::set_error("hg_server_create: bad argument");
     return HG_ERR_INVALID_ARG;
   }
+  try {
   auto sv = std::make_unique<hg_server>();
   sv->ctx = ctx;
   sv->budget = hbm_budget_bytes;
@@ -132,9 +143,24 @@ hg_status hg_server_create(hg_ctx* ctx, size_t hbm_budget_bytes, int32_t max_inf
     sv->streams.push_back(s);
   }
   hg_server* raw = sv.get();
-  for (int i = 0; i < max_inflight; ++i) sv->workers.emplace_back(worker_loop, raw, i);
+  try {
+    for (int i = 0; i < max_inflight; ++i) sv->workers.emplace_back(worker_loop, raw, i);
+  } catch (...) {  // stop the workers that did start before the server goes away
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->stopping = true;
+    }
+    sv->cv_work.notify_all();
+    for (auto& t : sv->workers) t.join();
+    for (auto x : sv->streams) (void)hipStreamDestroy(x);
+    throw;
+  }
   *out = sv.release();
   return HG_OK;
+  } catch (const std::exception& e) {
+    hg::set_error(std::string("hg_server_create: ") + e.what());
+    return HG_ERR_OUT_OF_MEMORY;
+  }
 }
 
 hg_status hg_server_submit(hg_server* sv, hg_problem* p, const hg_eval_desc* desc,
@@ -146,6 +172,7 @@ hg_status hg_server_submit(hg_server* sv, hg_problem* p, const hg_eval_desc* des
   size_t ws = 0;
   hg_status st = hg_eval_footprint(p, desc, &ws);
   if (st != HG_OK) return st;
+  try {
   auto r = std::make_shared<Request>();
   r->p = p;
   r->desc = *desc;
@@ -179,6 +206,10 @@ hg_status hg_server_submit(hg_server* sv, hg_problem* p, const hg_eval_desc* des
   }
   sv->cv_work.notify_one();
   return HG_OK;
+  } catch (const std::bad_alloc&) {
+    hg::set_error("hg_server_submit: host allocation failed");
+    return HG_ERR_OUT_OF_MEMORY;
+  }
 }
 
 hg_status hg_server_poll(hg_server* sv, uint64_t req_id, int32_t* done) {
