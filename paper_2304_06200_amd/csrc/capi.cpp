@@ -106,6 +106,21 @@ hg_status check_hermitian(const std::vector<std::vector<Entry>>& rows, const cha
 
 using namespace hg;
 
+// The C entry points below never let an exception out: a failed host
+// allocation becomes OUT_OF_MEMORY, anything else DEVICE.
+template <typename F>
+hg_status guarded(const char* what, F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(HG_ERR_OUT_OF_MEMORY, std::string(what) + ": host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(HG_ERR_DEVICE, std::string(what) + ": " + e.what());
+  } catch (...) {
+    return fail(HG_ERR_DEVICE, std::string(what) + ": unexpected exception");
+  }
+}
+
 hg_problem::~hg_problem() {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
@@ -159,7 +174,7 @@ hg_status hg_destroy(hg_ctx* ctx) {
   return HG_OK;
 }
 
-hg_status hg_problem_create(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, const hg_csr* H0,
+static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, const hg_csr* H0,
                             const hg_csr* Hk, const double* omega_diag, hg_problem** out) {
   if (!ctx || !out || !H0) return fail(HG_ERR_INVALID_ARG, "NULL argument");
   if (dim < 1 || dim > (int64_t)kMaxThreads * kMaxRows)
@@ -279,7 +294,7 @@ double hg_error_bound(double theta, int32_t m, int32_t s, int32_t sigma, double 
   return error_bound(theta, m, s, sigma, u);
 }
 
-hg_status hg_plan(const double* theta, int64_t n, int32_t sigma, double tau, double u,
+static hg_status plan_impl(const double* theta, int64_t n, int32_t sigma, double tau, double u,
                   int32_t* m_out, int32_t* s_out) {
   if (n < 0 || (n > 0 && (!theta || !m_out || !s_out)) || sigma < 1 || !(tau > 0.0) ||
       !(u > 0.0 && u < 0.25))
@@ -383,7 +398,7 @@ hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* d, size_t* 
   return HG_OK;
 }
 
-hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, double* grad,
+static hg_status eval_impl(hg_problem* p, const hg_eval_desc* d, hg_result* results, double* grad,
                   void* stream) {
   hg_status st = check_desc(p, d);
   if (st != HG_OK) return st;
@@ -538,6 +553,23 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, doub
     r.ms_backward = ms_b;
   }
   return HG_OK;
+}
+
+
+hg_status hg_problem_create(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, const hg_csr* H0,
+                            const hg_csr* Hk, const double* omega_diag, hg_problem** out) {
+  return guarded("hg_problem_create",
+                 [&] { return problem_create_impl(ctx, dim, n_ctrl, H0, Hk, omega_diag, out); });
+}
+
+hg_status hg_plan(const double* theta, int64_t n, int32_t sigma, double tau, double u,
+                  int32_t* m_out, int32_t* s_out) {
+  return guarded("hg_plan", [&] { return plan_impl(theta, n, sigma, tau, u, m_out, s_out); });
+}
+
+hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, double* grad,
+                  void* stream) {
+  return guarded("hg_eval", [&] { return eval_impl(p, d, results, grad, stream); });
 }
 
 }  // extern "C"
