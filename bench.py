@@ -221,6 +221,19 @@ def main():
             f"TFLOP/s, forward {r['tflops_forward']:.2f} TFLOP/s")
 
     main_r = out["c64"]
+    # streaming-SpMM model (each Taylor product streams H_n, reads its operand and
+    # writes its result): bytes per eval = sum_mu [(K+4)(nnz (c+4) + 2 d S c) + K(...E_k)]
+    def model_bytes(c):
+        mu = float(np.mean(out["c64"]["sum_mu"]))
+        per_a = nnz * (c + 4) + 2 * p.dim * p.n_states * c
+        per_e = sum(nnz_ctrl) / max(p.n_ctrl, 1) * (c + 4) + 2 * p.dim * p.n_states * c
+        return mu * ((p.n_ctrl + 4) * per_a + p.n_ctrl * per_e)
+    streaming = {}
+    for dtype, c in (("c64", 8), ("c128", 16)):
+        if dtype in out:
+            mb = model_bytes(c)
+            streaming[dtype] = {"model_bytes_per_eval": mb,
+                                "effective_TBps": mb * B / (out[dtype]["ms_per_step"] * 1e-3) / 1e12}
     line = {
         "metric": METRIC, "value": main_r["evals_per_s"], "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_r["ms_per_step"],
@@ -244,6 +257,13 @@ def main():
         line["c64_over_c128"] = main_r["evals_per_s"] / c["evals_per_s"]
     line["kernel_ms"] = {d: {"forward": out[d]["ms_forward"], "backward": out[d]["ms_backward"]}
                          for d in out}
+    streaming["note"] = ("bytes a streaming SpMM design would move; the sweep keeps its working set in "
+                         "LDS and registers, so this exceeds the 8 TB/s HBM peak")
+    line["streaming_model"] = streaming
+    # one evaluation alone (16 workgroups): its latency, next to the batched throughput
+    r1 = run_precision(hg, prob, u[:1], psi0, tg, p, "c64", 2, 1)
+    line["batch1_latency_ms"] = {"c64": r1["ms_per_step"], "concurrent_evals": 1}
+    log(f"[bench] c64 batch 1: {r1['ms_per_step']:.1f} ms per evaluation")
     # device memory of one evaluation (Table I): HG reconstruction keeps no state
     # history; checkpointing every step stores it (the stored-history comparator)
     from paper_2304_06200_amd import _lib as L
