@@ -60,11 +60,17 @@ def run_precision(hg, prob, u, psi0, tg, p, dtype, steps, warmup, w_int=0.0):
 
 
 def kernel_source_hash():
+    """sha256 (first 16 hex) of the sweep kernel sources with comments and
+    blank space removed: changes with the code, not with its comments."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("sweep_kernels.h", "sweep_units.h", "sweep_launch.hip"):
-        with open(os.path.join(ROOT, "paper_2304_06200_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2304_06200_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        h.update("\n".join(" ".join(l.split()) for l in text.splitlines() if l.strip()).encode())
     return h.hexdigest()[:16]
 
 

@@ -3,9 +3,11 @@
 // Work decomposition.  One workgroup owns one state column h of one
 // evaluation b for the whole time axis (the chain psi_0 -> psi_N is strictly
 // sequential, Sec. II).  Each thread owns RPT rows (row = tid + r*NT, so a
-// wavefront touches consecutive rows).  For step n the thread assembles its
-// rows of B_n = -i dt H_n / s_n on the W union diagonals into registers once
-// and reuses them for all m_n s_n Taylor terms.
+// wavefront touches consecutive rows); workgroups have 512 threads (2
+// wavefronts per SIMD) or, where registers allow, 1024 (4 per SIMD, which
+// hides the latency around each term's barrier).  For step n the thread
+// assembles its rows of B_n = -i dt H_n / s_n on the W union diagonals into
+// registers once and reuses them for all m_n s_n Taylor terms.
 //
 // Term vectors live in LDS as a *state block*: row i of the block holds the
 // V vectors that are propagated together (1 in the forward sweep, psi and
@@ -207,14 +209,15 @@ __device__ __forceinline__ void inv_table_to_lds(unsigned char* smem) {
 // complex64 or one complex128; a single complex64 vector uses 8-byte rows).
 // Consecutive lanes own consecutive rows, so one ds_read of a plane row per
 // (row, diagonal) is a contiguous, bank-conflict-free wave access.  Planes of
-// a buffer are PS rows apart, PS = RPT * 512 (the largest dimension for that
-// row count), a compile-time constant, so plane offsets fold into the
-// instruction's immediate offset.  Reads at row + off outside [0, d) land in
-// a neighbouring plane or in a zeroed guard of `halo` rows before the first and
-// after the last plane: finite data times a zero coefficient (the operator
-// diagonals are zero outside the matrix), so no bounds tests are needed.
-// Plane stride in rows: RPT * 512 when RPT <= 4 (a compile-time constant, so
-// plane offsets become immediates), else the dimension itself (runtime).
+// a buffer are PS rows apart.  The layout parameter `rpt` here counts rows per
+// 512 threads (a 1024-thread kernel with RPT rows per thread uses 2*RPT):
+// PS = rpt * 512, the largest dimension for that count, when rpt <= 4 (a
+// compile-time constant, so plane offsets fold into the instruction's
+// immediate offset), else the dimension itself (runtime).  Reads at row + off
+// outside [0, d) land in a neighbouring plane or in a zeroed guard of `halo`
+// rows before the first and after the last plane: finite data times a zero
+// coefficient (the operator diagonals are zero outside the matrix), so no
+// bounds tests are needed.
 __host__ __device__ constexpr int plane_rows(int rpt, int d) { return rpt <= 4 ? rpt * kMaxThreads : d; }
 __host__ __device__ constexpr int block_vp(int cs, int v) { return (16 / cs) < v ? (16 / cs) : v; }
 // Bytes of LDS of a double-buffered block of v vectors (both guards included).
@@ -502,8 +505,8 @@ __device__ __forceinline__ void renormalise(cx<R> (&p)[RPT], double* red) {
 // penalty partial sum_n <psi_n|Omega|psi_n> (App. A, eq. c2st) and the overlap
 // <phi_T|psi_N> (Sec. III.A) of this column.
 // TPB threads per workgroup; the LDS layout is that of LR = RPT*TPB/512 rows
-// per 512 threads, so the complex64 forward can run 1024 threads (4 waves per
-// SIMD, to hide the latency of its short, barrier-separated terms).
+// per 512 threads, so the forward can run 1024 threads (4 waves per SIMD, to
+// hide the latency of its short, barrier-separated terms).
 template <typename R, int RPT, int W, int TPB>
 __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
   using C = cx<R>;
