@@ -94,9 +94,30 @@ int32_t hg_version(void);
 hg_status hg_problem_create(hg_ctx* ctx, int64_t dim, int32_t n_ctrl,
                             const hg_csr* H0, const hg_csr* Hk,
                             const double* omega_diag, hg_problem** out);
+
+/* The same problem with every operator stored as a dense dim x dim matrix, as
+ * the paper's runtime and memory benchmarks store the Hamiltonian (Sec. IV.B;
+ * Theta(d^2) memory, Sec. IV.A).  hg_eval then runs the dense path: each
+ * Taylor term of the forward, reconstruction, co-state and auxiliary-matrix
+ * actions (Sec. III.B-C) is one dense complex contraction of the embedded
+ * 2d x 2d operator with the whole block of states, on the matrix cores
+ * (FP32 MFMA for HG_C64, FP64 MFMA for HG_C128).  Meant for wide state blocks
+ * (full-basis gate problems, S = d) and operators that are dense or have
+ * more diagonals than the DIA kernels take.  Inputs, validation, sigma' (from
+ * the structural pattern), results and precision rules are those of
+ * hg_problem_create; only HG_MODE_RECONSTRUCT is built for dense storage
+ * (hg_eval returns UNSUPPORTED for the checkpoint mode).  Device memory:
+ * (n_ctrl+1) dp^2 complex128 here, dp = dim rounded up to 64; per evaluation
+ * the embedded operators and the state blocks (hg_eval_footprint).
+ * Errors: INVALID_ARG, NOT_HERMITIAN, NONFINITE, UNSUPPORTED (dim > 8192,
+ * n_ctrl > 16), OUT_OF_MEMORY, DEVICE. */
+hg_status hg_problem_create_dense(hg_ctx* ctx, int64_t dim, int32_t n_ctrl,
+                                  const hg_csr* H0, const hg_csr* Hk,
+                                  const double* omega_diag, hg_problem** out);
 hg_status hg_problem_destroy(hg_problem* p);
 
-/* Problem facts: dim, n_ctrl, number of union diagonals, sigma' (the
+/* Problem facts: dim, n_ctrl, number of union diagonals (0 for dense
+ * storage), sigma' (the
  * largest number of non-zeros in a row of the union pattern, App. C eq.
  * sigmapdef) and the number of stored union non-zeros.  Any pointer may be NULL. */
 hg_status hg_problem_info(const hg_problem* p, int64_t* dim, int32_t* n_ctrl,

@@ -82,6 +82,9 @@ def _load():
         "hg_version": (C.c_int32, []),
         "hg_problem_create": (C.c_int, [P, C.c_int64, C.c_int32, C.POINTER(hg_csr),
                                         C.POINTER(hg_csr), C.POINTER(C.c_double), C.POINTER(P)]),
+        "hg_problem_create_dense": (C.c_int, [P, C.c_int64, C.c_int32, C.POINTER(hg_csr),
+                                              C.POINTER(hg_csr), C.POINTER(C.c_double),
+                                              C.POINTER(P)]),
         "hg_problem_destroy": (C.c_int, [P]),
         "hg_problem_info": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -111,7 +114,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("hg_create", "hg_destroy", "hg_status_string", "hg_last_error", "hg_version",
-            "hg_problem_create", "hg_problem_destroy", "hg_problem_info", "hg_plan",
+            "hg_problem_create", "hg_problem_create_dense", "hg_problem_destroy", "hg_problem_info", "hg_plan",
             "hg_error_bound", "hg_step_norms", "hg_eval", "hg_eval_footprint",
             "hg_server_create", "hg_server_submit", "hg_server_poll", "hg_server_wait",
             "hg_server_cancel", "hg_server_info", "hg_server_destroy")
@@ -150,6 +153,15 @@ def hg_problem_create(ctx: int, dim: int, n_ctrl: int, H0: hg_csr, Hk, omega_dia
     om = omega_diag.ctypes.data_as(C.POINTER(C.c_double)) if omega_diag is not None else None
     _check(_lib.hg_problem_create(ctx, dim, n_ctrl, C.byref(H0), arr, om, C.byref(out)),
            "hg_problem_create")
+    return out.value
+
+
+def hg_problem_create_dense(ctx: int, dim: int, n_ctrl: int, H0: hg_csr, Hk, omega_diag) -> int:
+    out = C.c_void_p()
+    arr = (hg_csr * max(n_ctrl, 1))(*Hk) if n_ctrl > 0 else None
+    om = omega_diag.ctypes.data_as(C.POINTER(C.c_double)) if omega_diag is not None else None
+    _check(_lib.hg_problem_create_dense(ctx, dim, n_ctrl, C.byref(H0), arr, om, C.byref(out)),
+           "hg_problem_create_dense")
     return out.value
 
 

@@ -53,16 +53,23 @@ def _csr_struct(m, dim: int, keep: list) -> L.hg_csr:
 
 class Problem:
     """Drift H0, controls Hk and an optional diagonal penalty Omega, copied to
-    the device (immutable; may be shared by concurrent evaluations)."""
+    the device (immutable; may be shared by concurrent evaluations).
 
-    def __init__(self, ctx: Context, H0, Hk: Sequence, omega: Optional[np.ndarray] = None):
+    dense=False stores the operators by diagonals (sparse, banded problems);
+    dense=True stores them as dense matrices and evaluations run the MFMA
+    path (wide state blocks, dense operators)."""
+
+    def __init__(self, ctx: Context, H0, Hk: Sequence, omega: Optional[np.ndarray] = None,
+                 dense: bool = False):
         self.ctx = ctx
         dim = H0.shape[0]
         keep: list = []
         h0 = _csr_struct(H0, dim, keep)
         hk = [_csr_struct(h, dim, keep) for h in Hk]
         om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
-        self.handle = L.hg_problem_create(ctx.handle, dim, len(Hk), h0, hk, om)
+        create = L.hg_problem_create_dense if dense else L.hg_problem_create
+        self.handle = create(ctx.handle, dim, len(Hk), h0, hk, om)
+        self.dense = dense
         self.info = L.hg_problem_info(self.handle)
         self.dim = dim
         self.n_ctrl = len(Hk)

@@ -127,6 +127,7 @@ hg_problem::~hg_problem() {
   if (ops.vals) (void)hipFree(ops.vals);
   if (ops.valk) (void)hipFree(ops.valk);
   if (ops.omega) (void)hipFree(ops.omega);
+  if (dops.H) (void)hipFree(dops.H);
 }
 
 extern "C" {
@@ -175,11 +176,13 @@ hg_status hg_destroy(hg_ctx* ctx) {
 }
 
 static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, const hg_csr* H0,
-                            const hg_csr* Hk, const double* omega_diag, hg_problem** out) {
+                            const hg_csr* Hk, const double* omega_diag, bool dense,
+                            hg_problem** out) {
   if (!ctx || !out || !H0) return fail(HG_ERR_INVALID_ARG, "NULL argument");
-  if (dim < 1 || dim > (int64_t)kMaxThreads * kMaxRows)
+  const int64_t dmax = dense ? (int64_t)kDenseMaxDim : (int64_t)kMaxThreads * kMaxRows;
+  if (dim < 1 || dim > dmax)
     return fail(dim < 1 ? HG_ERR_INVALID_ARG : HG_ERR_UNSUPPORTED,
-                "dim must be in [1, " + std::to_string(kMaxThreads * kMaxRows) + "]");
+                "dim must be in [1, " + std::to_string(dmax) + "]");
   if (n_ctrl < 0 || n_ctrl > kMaxCtrl)
     return fail(n_ctrl < 0 ? HG_ERR_INVALID_ARG : HG_ERR_UNSUPPORTED, "n_ctrl out of range");
   if (n_ctrl > 0 && !Hk) return fail(HG_ERR_INVALID_ARG, "Hk is NULL");
@@ -219,6 +222,33 @@ static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, c
     nnz += (int64_t)cols.size();
   }
   if (uoff.empty()) uoff.insert(0);
+  if (dense) {
+    // dense storage: H[o][i][j] row-major, padded to dp = dim rounded up to 64
+    auto p = std::make_unique<hg_problem>();
+    p->ctx = ctx;
+    p->dim = dim;
+    p->n_ctrl = K;
+    p->sigma = (int32_t)std::max<int64_t>(sigma, 1);
+    p->nnz = nnz;
+    p->nnz_ctrl = nnz_ctrl;
+    p->dense = true;
+    p->dp = (dim + 63) / 64 * 64;
+    const size_t dp = (size_t)p->dp, plane = dp * dp;
+    std::vector<double2> hd((size_t)(K + 1) * plane, double2{0.0, 0.0});
+    for (int o = 0; o <= K; ++o)
+      for (int64_t i = 0; i < dim; ++i)
+        for (auto& en : ops[o][i]) hd[(size_t)o * plane + (size_t)i * dp + en.col] = double2{en.re, en.im};
+    if (hipMalloc(&p->dops.H, hd.size() * sizeof(double2)) != hipSuccess)
+      return fail(HG_ERR_OUT_OF_MEMORY, "dense operators: " + std::to_string(hd.size() * 16) + " bytes");
+    HG_HIP(hipMemcpy(p->dops.H, hd.data(), hd.size() * sizeof(double2), hipMemcpyHostToDevice));
+    if (omega_diag) {
+      HG_HIP(hipMalloc(&p->ops.omega, dim * sizeof(double)));
+      HG_HIP(hipMemcpy(p->ops.omega, omega_diag, dim * sizeof(double), hipMemcpyHostToDevice));
+      p->dops.omega = p->ops.omega;
+    }
+    *out = p.release();
+    return HG_OK;
+  }
   if ((int)uoff.size() > kMaxDiag)
     return fail(HG_ERR_UNSUPPORTED, "union pattern has " + std::to_string(uoff.size()) +
                                         " diagonals; the DIA kernels support at most 13");
@@ -283,7 +313,7 @@ hg_status hg_problem_info(const hg_problem* p, int64_t* dim, int32_t* n_ctrl, in
   if (!p) return fail(HG_ERR_INVALID_ARG, "problem is NULL");
   if (dim) *dim = p->dim;
   if (n_ctrl) *n_ctrl = p->n_ctrl;
-  if (ell_width) *ell_width = p->ops.W;
+  if (ell_width) *ell_width = p->dense ? 0 : p->ops.W;
   if (sigma) *sigma = p->sigma;
   if (nnz) *nnz = p->nnz;
   return HG_OK;
@@ -326,16 +356,35 @@ hg_status hg_step_norms(hg_problem* p, const double* u, int32_t n_batch, int32_t
     return fail(HG_ERR_INVALID_ARG, "hg_step_norms: bad argument");
   if (!std::isfinite(dt) || !(dt > 0.0)) return fail(HG_ERR_INVALID_ARG, "dt must be finite and > 0");
   HG_HIP(hipSetDevice(p->ctx->device));
-  HG_HIP(launch_step_norms(p->ops, (int)p->dim, p->n_ctrl, u, n_batch, n_steps, dt, theta_out,
-                           (hipStream_t)stream));
+  if (p->dense)
+    HG_HIP(launch_dense_norms(p->dops, (int)p->dim, (int)p->dp, p->n_ctrl, u, n_batch, n_steps, dt,
+                              theta_out, (hipStream_t)stream));
+  else
+    HG_HIP(launch_step_norms(p->ops, (int)p->dim, p->n_ctrl, u, n_batch, n_steps, dt, theta_out,
+                             (hipStream_t)stream));
   return HG_OK;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Workspace {
-  size_t theta, pnorm, sched, psiN, cold, ckpt, segbuf, ovl, ovt, gt, pen, gradp, drift, res, total;
+  size_t theta, pnorm, sched, psiN, cold, ckpt, segbuf, ovl, ovt, gt, pen, gradp, drift, res;
+  size_t mat, emat, blocks;  // dense path
+  size_t total;
 };
+
+static DenseShape dense_shape(const hg_problem* p, int B, int N, int S, bool c128) {
+  DenseShape sh{};
+  sh.d = (int)p->dim;
+  sh.dp = (int)p->dp;
+  sh.K = p->n_ctrl;
+  sh.N = N;
+  sh.S = S;
+  sh.Sp = (S + 63) / 64 * 64;
+  sh.B = B;
+  sh.c128 = c128;
+  return sh;
+}
 
 static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128, int ckpt_every,
                         bool integrated) {
@@ -351,8 +400,9 @@ static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128, int
   w.theta = take((size_t)B * N * 8);
   w.pnorm = take((size_t)B * S * 8);
   w.sched = take((size_t)2 * B * N * 4);
-  w.psiN = take((size_t)B * S * d * cs);
-  w.cold = take((size_t)B * S * 3 * d * cs);
+  const bool dn = p->dense;
+  w.psiN = take(dn ? 0 : (size_t)B * S * d * cs);
+  w.cold = take(dn ? 0 : (size_t)B * S * 3 * d * cs);
   const size_t C = ckpt_every > 0 ? (size_t)std::min(ckpt_every, N) : 0;
   const size_t nseg = ckpt_every > 0 ? ((size_t)N + ckpt_every - 1) / ckpt_every : 0;
   w.ckpt = take((size_t)B * S * nseg * d * cs);
@@ -361,9 +411,16 @@ static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128, int
   w.ovt = take(integrated ? (size_t)B * S * N * 16 : 0);
   w.gt = take(integrated ? (size_t)B * N * 16 : 0);
   w.pen = take((size_t)B * S * 8);
-  w.gradp = take((size_t)B * S * std::max<size_t>(K, 1) * N * 8);
+  w.gradp = take(dn ? 0 : (size_t)B * S * std::max<size_t>(K, 1) * N * 8);
   w.drift = take((size_t)B * S * 8);
   w.res = take((size_t)B * 8 * 8);
+  if (dn) {
+    const DenseShape sh = dense_shape(p, B, N, S, c128);
+    const size_t rs = cs / 2, Mp = 2 * (size_t)sh.dp;
+    w.mat = take((size_t)B * Mp * Mp * rs);
+    w.emat = take((size_t)B * K * Mp * Mp * rs);
+    w.blocks = take(dense_block_elems(sh) * rs);
+  }
   w.total = o;
   return w;
 }
@@ -385,6 +442,8 @@ static hg_status check_desc(const hg_problem* p, const hg_eval_desc* d) {
   if (d->renorm_every < 0) return fail(HG_ERR_INVALID_ARG, "renorm_every must be >= 0");
   if ((p->n_ctrl > 0 && !d->u) || !d->psi0 || !d->targets)
     return fail(HG_ERR_INVALID_ARG, "NULL device array");
+  if (p->dense && d->mode != HG_MODE_RECONSTRUCT)
+    return fail(HG_ERR_UNSUPPORTED, "dense storage: only the reconstruction mode is built");
   return HG_OK;
 }
 
@@ -410,7 +469,8 @@ static hg_status eval_impl(hg_problem* p, const hg_eval_desc* d, hg_result* resu
 
   SweepShape sh{};
   std::string why;
-  if (!sweep_supported(p->ops, (int)p->dim, K, c128, p->ctx->lds_per_block, &sh, &why))
+  if (!p->dense &&
+      !sweep_supported(p->ops, (int)p->dim, K, c128, p->ctx->lds_per_block, &sh, &why))
     return fail(HG_ERR_UNSUPPORTED, why);
   sh.n_steps = N;
   sh.n_states = S;
@@ -457,7 +517,10 @@ static hg_status eval_impl(hg_problem* p, const hg_eval_desc* d, hg_result* resu
   if (K == 0) u_dev = d_theta;  // never read (no controls); any valid pointer
 
   // 1-norms of every step (App. C) and state norms, then the host planner
-  HG_HIP(launch_step_norms(p->ops, (int)p->dim, K, u_dev, B, N, d->dt, d_theta, hs));
+  if (p->dense)
+    HG_HIP(launch_dense_norms(p->dops, (int)p->dim, (int)p->dp, K, u_dev, B, N, d->dt, d_theta, hs));
+  else
+    HG_HIP(launch_step_norms(p->ops, (int)p->dim, K, u_dev, B, N, d->dt, d_theta, hs));
   HG_HIP(launch_state_norms(d->psi0, (int)p->dim, S, B, d_pnorm, hs));
   HG_HIP(hipMemcpyAsync(h_theta, d_theta, (size_t)B * N * 8, hipMemcpyDeviceToHost, hs));
   HG_HIP(hipMemcpyAsync(h_pnorm, d_pnorm, (size_t)B * S * 8, hipMemcpyDeviceToHost, hs));
@@ -517,7 +580,28 @@ static hg_status eval_impl(hg_problem* p, const hg_eval_desc* d, hg_result* resu
   if (d->flags & HG_FLAG_TIMING)
     for (int i = 0; i < 3; ++i) HG_HIP(hipEventCreate(&bf.ev[i]));
   SweepParams sp{d->dt, d->w_fid, d->w_pen, d->w_int, d->renorm_every, ck};
-  HG_HIP(launch_sweep(p->ops, sh, bf, sp, hs));
+  if (p->dense) {
+    DenseBuffers db{};
+    db.u = u_dev;
+    db.m_sched = bf.m_sched;
+    db.s_sched = bf.s_sched;
+    db.psi0 = d->psi0;
+    db.targets = d->targets;
+    db.blocks = ws + w.blocks;
+    db.mat = ws + w.mat;
+    db.emat = ws + w.emat;
+    db.pen = bf.pen;
+    db.ovl = bf.ovl;
+    db.ovt = bf.ovt;
+    db.gt = bf.gt;
+    db.drift = bf.drift;
+    db.res = bf.res;
+    db.grad = grad;
+    for (int i = 0; i < 3; ++i) db.ev[i] = bf.ev[i];
+    HG_HIP(launch_dense_sweep(p->dops, dense_shape(p, B, N, S, c128), db, sp, h_m, h_s, hs));
+  } else {
+    HG_HIP(launch_sweep(p->ops, sh, bf, sp, hs));
+  }
   HG_HIP(hipMemcpyAsync(h_res, bf.res, (size_t)B * 8 * 8, hipMemcpyDeviceToHost, hs));
   HG_HIP(hipMemcpyAsync(h_drift, bf.drift, (size_t)B * S * 8, hipMemcpyDeviceToHost, hs));
   HG_HIP(hipStreamSynchronize(hs));
@@ -558,8 +642,16 @@ static hg_status eval_impl(hg_problem* p, const hg_eval_desc* d, hg_result* resu
 
 hg_status hg_problem_create(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, const hg_csr* H0,
                             const hg_csr* Hk, const double* omega_diag, hg_problem** out) {
-  return guarded("hg_problem_create",
-                 [&] { return problem_create_impl(ctx, dim, n_ctrl, H0, Hk, omega_diag, out); });
+  return guarded("hg_problem_create", [&] {
+    return problem_create_impl(ctx, dim, n_ctrl, H0, Hk, omega_diag, false, out);
+  });
+}
+
+hg_status hg_problem_create_dense(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, const hg_csr* H0,
+                                  const hg_csr* Hk, const double* omega_diag, hg_problem** out) {
+  return guarded("hg_problem_create_dense", [&] {
+    return problem_create_impl(ctx, dim, n_ctrl, H0, Hk, omega_diag, true, out);
+  });
 }
 
 hg_status hg_plan(const double* theta, int64_t n, int32_t sigma, double tau, double u,

@@ -36,6 +36,16 @@ struct DevOps {
   double* omega = nullptr;         // [dim] or nullptr
 };
 
+constexpr int kDenseMaxDim = 8192;  // dense storage: (K+1) dp^2 complex128 on the device
+
+// Operators on the device as dense matrices (problems created with dense
+// storage): H[o][i][j], o = 0 (H0) then 1..K, row-major, dp = dim rounded up to
+// 64, zero outside dim x dim.
+struct DenseOps {
+  double2* H = nullptr;
+  double* omega = nullptr;  // [dim] or nullptr (the problem's penalty diagonal)
+};
+
 }  // namespace hg
 
 struct hg_ctx {
@@ -52,6 +62,9 @@ struct hg_problem {
   int64_t nnz = 0;                 // stored union non-zeros (structural)
   std::vector<int64_t> nnz_ctrl;   // structural non-zeros of each H_k
   hg::DevOps ops;
+  bool dense = false;              // dense storage: the MFMA path runs, not the DIA kernels
+  int64_t dp = 0;                  // padded dimension of the dense matrices
+  hg::DenseOps dops;
   ~hg_problem();                   // frees the device arrays (also on a failed creation)
 };
 
@@ -107,5 +120,35 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
                      SweepShape* shape, std::string* why);
 hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuffers& b,
                         const SweepParams& p, hipStream_t st);
+
+// Dense path (dense_kernels.hip).
+struct DenseShape {
+  int d, dp, K, N, S, Sp, B;  // Sp = S rounded up to 64
+  bool c128;
+};
+struct DenseBuffers {
+  const double* u;
+  const int32_t* m_sched;          // [B][N]
+  const int32_t* s_sched;          // [B][N]
+  const double* psi0;              // [B][S][dim] complex128
+  const double* targets;           // [B][S][dim] complex128
+  void* blocks;                    // dense_block_elems(shape) working-precision reals
+  void* mat;                       // [B][2dp][2dp] embedded A_n/s_n
+  void* emat;                      // [B][K][2dp][2dp] embedded E_k/s_n
+  double* pen;                     // [B][S]
+  double* ovl;                     // [B][S][2]
+  double* ovt;                     // [B][S][N][2] or null (w_int == 0)
+  double* gt;                      // [B][N][2] (with ovt)
+  double* drift;                   // [B][S]
+  double* res;                     // [B][8]
+  double* grad;                    // [B][K][N] or nullptr (then no derivative sweep)
+  hipEvent_t ev[3];
+};
+size_t dense_block_elems(const DenseShape& sh);
+hipError_t launch_dense_norms(const DenseOps& ops, int d, int dp, int K, const double* u, int nb,
+                              int N, double dt, double* theta, hipStream_t st);
+hipError_t launch_dense_sweep(const DenseOps& ops, const DenseShape& sh, const DenseBuffers& bf,
+                              const SweepParams& sp, const int32_t* h_m, const int32_t* h_s,
+                              hipStream_t st);
 
 }  // namespace hg
