@@ -174,7 +174,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-integrated", action="store_true",
                     help="skip the leg with the time-integrated infidelity term")
-    ap.add_argument("--gate-batch", type=int, default=4,
+    ap.add_argument("--gate-batch", type=int, default=8,
                     help="concurrent evaluations of the dense-storage gate leg")
     ap.add_argument("--no-gate", action="store_true",
                     help="skip the full-basis gate leg (three coupled transmons)")

@@ -31,9 +31,9 @@
 namespace hg {
 namespace {
 
-constexpr int kBM = 128;  // rows of the output tile (embedded rows)
-constexpr int kBN = 64;   // columns of the output tile (states)
-constexpr int kTPB = 256; // 4 wavefronts, 2 x 2 over the tile (64 x 32 each)
+constexpr int kTPB = 256; // 4 wavefronts, 2 x 2 over the output tile
+// Output tile: 32*WM rows (embedded rows) x 32*WN columns (states); each
+// wavefront computes 16*WM x 16*WN as WM x WN MFMA tiles of 16 x 16.
 
 template <typename R>
 struct Mf;
@@ -91,11 +91,13 @@ struct TermArgs {
 };
 
 // One Taylor term for every group of every evaluation of the batch.
-// Grid: x = column tiles of 64 over G*Sp, y = row tiles of 128 over Mp, z = b.
+// Grid: x = column tiles of 32*WN over G*Sp, y = row tiles of 32*WM over Mp, z = b.
 // A workgroup whose evaluation has fewer terms (j > m_b) or repetitions
 // (rep > s_b) at this step returns at once.
-template <typename R>
+template <typename R, int WM, int WN>
 __global__ void __launch_bounds__(kTPB) k_term(TermArgs<R> a) {
+  constexpr int kBM = 32 * WM;
+  constexpr int kBN = 32 * WN;
   using M = Mf<R>;
   using v4 = typename M::v4;
   constexpr int BK = M::BK;
@@ -119,7 +121,9 @@ __global__ void __launch_bounds__(kTPB) k_term(TermArgs<R> a) {
   const int nk1 = Mp / BK;
   const int nk = (a.aux && g > 0) ? 2 * nk1 : nk1;
 
-  uint4 ra[4], rx[2];
+  constexpr int AQ = kBM * RV / kTPB;  // 16-byte A vectors per thread and slab
+  constexpr int XQ = kBN * RV / kTPB;  // 16-byte X vectors per thread and slab
+  uint4 ra[AQ], rx[XQ];  // the next slab, in flight while this one is computed
   auto gload = [&](int t) {
     const R* A;
     const R* X;
@@ -134,41 +138,36 @@ __global__ void __launch_bounds__(kTPB) k_term(TermArgs<R> a) {
       k0 = (t - nk1) * BK;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < AQ; ++q) {
       const int f = tid + kTPB * q, row = f / RV, cv = f % RV;
       ra[q] = *reinterpret_cast<const uint4*>(A + (size_t)(i0 + row) * Mp + k0 + cv * VE);
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < XQ; ++q) {
       const int f = tid + kTPB * q, col = f / RV, cv = f % RV;
       rx[q] = *reinterpret_cast<const uint4*>(X + (size_t)col * Mp + k0 + cv * VE);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < AQ; ++q) {
       const int f = tid + kTPB * q, row = f / RV, cv = f % RV;
       *reinterpret_cast<uint4*>(&As[buf][row * LS + cv * VE]) = ra[q];
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < XQ; ++q) {
       const int f = tid + kTPB * q, col = f / RV, cv = f % RV;
       *reinterpret_cast<uint4*>(&Xs[buf][col * LS + cv * VE]) = rx[q];
     }
   };
 
-  v4 acc[4][2];
+  v4 acc[WM][WN];
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = v4{0, 0, 0, 0};
+    for (int ni = 0; ni < WN; ++ni) acc[mi][ni] = v4{0, 0, 0, 0};
 
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int t = 0; t < nk; ++t) {
-    const int buf = t & 1;
-    if (t + 1 < nk) gload(t + 1);
+  auto compute = [&](int buf) {
     const R* Ab = As[buf];
     const R* Xb = Xs[buf];
     // Within a chunk of 16 k, MFMA step q takes k = kc + 4*lg + q from lane
@@ -176,19 +175,31 @@ __global__ void __launch_bounds__(kTPB) k_term(TermArgs<R> a) {
     // and X use the same permutation of k, so the sum over k is unchanged.
 #pragma unroll
     for (int kc = 0; kc < BK; kc += 16) {
-      R av[4][4], xv[2][4];
+      R av[WM][4], xv[WN][4];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi) ld4(Ab + (wm * 64 + mi * 16 + lr) * LS + kc + 4 * lg, av[mi]);
+      for (int mi = 0; mi < WM; ++mi)
+        ld4(Ab + (wm * 16 * WM + mi * 16 + lr) * LS + kc + 4 * lg, av[mi]);
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni) ld4(Xb + (wn * 32 + ni * 16 + lr) * LS + kc + 4 * lg, xv[ni]);
+      for (int ni = 0; ni < WN; ++ni)
+        ld4(Xb + (wn * 16 * WN + ni * 16 + lr) * LS + kc + 4 * lg, xv[ni]);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi)
+        for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = M::mma(av[mi][q], xv[ni][q], acc[mi][ni]);
+          for (int ni = 0; ni < WN; ++ni) acc[mi][ni] = M::mma(av[mi][q], xv[ni][q], acc[mi][ni]);
     }
-    if (t + 1 < nk) sstore(buf ^ 1);
+  };
+  // slab t is computed from LDS buffer t&1 while slab t+1 loads into
+  // registers; it is stored to the other buffer after the compute.  (A second
+  // register stage, two slabs ahead, measured slower.)
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    if (t + 1 < nk) gload(t + 1);
+    compute(t & 1);
+    if (t + 1 < nk) sstore((t + 1) & 1);
     __syncthreads();
   }
 
@@ -197,17 +208,35 @@ __global__ void __launch_bounds__(kTPB) k_term(TermArgs<R> a) {
   R* ao = a.accout + (size_t)b * a.blk_b;
   R* to = a.tout + (size_t)b * a.blk_b;
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) {
-      const int col = c0 + wn * 32 + ni * 16 + lr;
+    for (int ni = 0; ni < WN; ++ni) {
+      const int col = c0 + wn * 16 * WN + ni * 16 + lr;
+      if constexpr (sizeof(R) == 4) {
+        // complex64: the lane's four rows are contiguous, one 16-byte access each
+        const size_t o = (size_t)col * Mp + i0 + wm * 16 * WM + mi * 16 + 4 * lg;
+        const float4 p = *reinterpret_cast<const float4*>(ai + o);
+        float4 t;
+        t.x = a.scale * acc[mi][ni][0];
+        t.y = a.scale * acc[mi][ni][1];
+        t.z = a.scale * acc[mi][ni][2];
+        t.w = a.scale * acc[mi][ni][3];
+        *reinterpret_cast<float4*>(to + o) = t;
+        float4 q;
+        q.x = p.x + t.x;
+        q.y = p.y + t.y;
+        q.z = p.z + t.z;
+        q.w = p.w + t.w;
+        *reinterpret_cast<float4*>(ao + o) = q;
+      } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const size_t o = (size_t)col * Mp + i0 + wm * 64 + mi * 16 + M::row(lg, r);
-        const R t = a.scale * acc[mi][ni][r];
-        const R p = ai[o];
-        to[o] = t;
-        ao[o] = p + t;
+        for (int r = 0; r < 4; ++r) {
+          const size_t o = (size_t)col * Mp + i0 + wm * 16 * WM + mi * 16 + M::row(lg, r);
+          const R t = a.scale * acc[mi][ni][r];
+          const R p = ai[o];
+          to[o] = t;
+          ao[o] = p + t;
+        }
       }
     }
 }
@@ -538,7 +567,11 @@ hipError_t taylor(const DenseShape& sh, const Rot<R>& r, int G, int aux, R sgn, 
   a.N = sh.N;
   a.msch = msch;
   a.ssch = ssch;
-  const dim3 grid((unsigned)(G * sh.Sp / kBN), (unsigned)(Mp / kBM), (unsigned)sh.B);
+  // 128 x 64 tiles, measured fastest: 128 x 128 loads a third fewer operand
+  // bytes per flop but halves the workgroups; 64 x 64 fits four workgroups per
+  // CU but does half the MFMA work per LDS read and per barrier
+  constexpr int WN = 2, WM = 4;
+  const dim3 grid((unsigned)(G * sh.Sp / (32 * WN)), (unsigned)(Mp / (32 * WM)), (unsigned)sh.B);
   const size_t cnt = (size_t)G * sh.Sp * Mp;
   for (int rep = 1; rep <= smax; ++rep) {
     for (int j = 1; j <= mmax; ++j) {
@@ -549,7 +582,7 @@ hipError_t taylor(const DenseShape& sh, const Rot<R>& r, int G, int aux, R sgn, 
       a.accout = r.A;
       a.tout = r.T[j & 1];
       a.scale = sgn / (R)j;
-      hipLaunchKernelGGL(k_term<R>, grid, dim3(kTPB), 0, st, a);
+      hipLaunchKernelGGL((k_term<R, WM, WN>), grid, dim3(kTPB), 0, st, a);
     }
     hipLaunchKernelGGL(k_dense_copy<R>, dim3(stride_blocks(cnt), sh.B), dim3(256), 0, st,
                        (const R*)r.A, r.P, r.stride, r.stride, cnt, ssch, sh.N, n, rep);
