@@ -132,3 +132,17 @@ def test_dense_rejects_checkpoint_mode():
     with pytest.raises(hg._lib.HGError) as e:
         _run(p, "c128", mode="checkpoint", ckpt_every=2)
     assert e.value.status == L.HG_ERR_UNSUPPORTED
+
+
+def test_dense_no_controls():
+    """K = 0 (drift only): cost, overlap and penalty against the oracle; no gradient."""
+    from oracle import grape
+    p = _random_dense(11, 45, 3, 0, 4)
+    ref = grape.cost_and_grad(p.H0, p.Hk, p.u, p.dt, p.psi0, p.targets, omega=p.omega,
+                              w_fid=p.w_fid, w_pen=p.w_pen)
+    for dtype in ("c128", "c64"):
+        r = _run(p, dtype)
+        log(f"[case] dense K=0 {dtype}: cost {r.cost[0]:.15g} ref {float(ref['cost']):.15g}")
+        assert r.grad is None
+        assert rel(r.cost[0], float(ref["cost"])) <= TOL[dtype]
+        assert abs(r.overlap[0] - ref["overlap"]) <= TOL[dtype]
