@@ -249,9 +249,10 @@ static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, c
     *out = p.release();
     return HG_OK;
   }
-  if ((int)uoff.size() > kMaxDiag)
+  if ((int)uoff.size() > kMaxDiagKernels)
     return fail(HG_ERR_UNSUPPORTED, "union pattern has " + std::to_string(uoff.size()) +
-                                        " diagonals; the DIA kernels support at most 13");
+                                        " diagonals; the DIA kernels support at most 13 "
+                                        "(hg_problem_create_dense stores operators densely)");
   for (int k = 0; k < K; ++k)
     if ((int)koff[k].size() > kMaxDiagCtrl)
       return fail(HG_ERR_UNSUPPORTED, "control " + std::to_string(k + 1) + " has " +

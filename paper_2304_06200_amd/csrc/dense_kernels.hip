@@ -229,14 +229,28 @@ __global__ void __launch_bounds__(kTPB) k_term(TermArgs<R> a) {
         q.w = p.w + t.w;
         *reinterpret_cast<float4*>(ao + o) = q;
       } else {
+        // complex128: element r of lane group lg is row lg + 4r.  A 4 x 4 exchange
+        // across the lane groups of each column (round q: read group (lg+q)&3,
+        // which sends its element lg) gives each lane rows 4lg .. 4lg+3.
+        const double v0 = a.scale * acc[mi][ni][0], v1 = a.scale * acc[mi][ni][1];
+        const double v2 = a.scale * acc[mi][ni][2], v3 = a.scale * acc[mi][ni][3];
+        auto sel = [](int i, double x0, double x1, double x2, double x3) {
+          return i == 0 ? x0 : i == 1 ? x1 : i == 2 ? x2 : x3;
+        };
+        double rc[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const size_t o = (size_t)col * Mp + i0 + wm * 16 * WM + mi * 16 + M::row(lg, r);
-          const R t = a.scale * acc[mi][ni][r];
-          const R p = ai[o];
-          to[o] = t;
-          ao[o] = p + t;
-        }
+        for (int q = 0; q < 4; ++q)
+          rc[q] = __shfl(sel((lg - q) & 3, v0, v1, v2, v3), lr + 16 * ((lg + q) & 3), 64);
+        double t[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t[r] = sel((r - lg) & 3, rc[0], rc[1], rc[2], rc[3]);
+        const size_t o = (size_t)col * Mp + i0 + wm * 16 * WM + mi * 16 + 4 * lg;
+        const double2 p0 = *reinterpret_cast<const double2*>(ai + o);
+        const double2 p1 = *reinterpret_cast<const double2*>(ai + o + 2);
+        *reinterpret_cast<double2*>(to + o) = double2{t[0], t[1]};
+        *reinterpret_cast<double2*>(to + o + 2) = double2{t[2], t[3]};
+        *reinterpret_cast<double2*>(ao + o) = double2{p0.x + t[0], p0.y + t[1]};
+        *reinterpret_cast<double2*>(ao + o + 2) = double2{p1.x + t[2], p1.y + t[3]};
       }
     }
 }

@@ -12,7 +12,8 @@
 
 namespace hg {
 
-constexpr int kMaxDiag = 16;      // diagonals of the union pattern (DIA width)
+constexpr int kMaxDiag = 16;      // storage for the union diagonals (DIA width)
+constexpr int kMaxDiagKernels = 13;  // widest union pattern the sweep kernels are built for
 constexpr int kMaxDiagCtrl = 4;   // diagonals of one control operator
 constexpr int kMaxCtrl = 16;      // control channels
 constexpr int kMaxThreads = 512;  // threads per workgroup (2 waves per SIMD)

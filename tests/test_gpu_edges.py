@@ -176,6 +176,12 @@ def test_error_paths():
     with pytest.raises(L.HGError) as e:
         hg.Problem(context(), dense, [], None)
     assert e.value.status == L.HG_ERR_UNSUPPORTED
+    # 15 diagonals: within the DIA storage but wider than the kernels, rejected at creation
+    band = sp.diags([np.ones(40 - abs(o)) for o in range(-7, 8)], list(range(-7, 8)),
+                    dtype=complex).tocsr()
+    with pytest.raises(L.HGError) as e:
+        hg.Problem(context(), band, [], None)
+    assert e.value.status == L.HG_ERR_UNSUPPORTED and "13" in str(e.value)
     # the evaluation still works after the errors
     r = hg.evaluate(prob, u, psi0, tg, p.dt)
     assert np.isfinite(r.cost[0])
