@@ -108,3 +108,26 @@ def test_cancel_queued_request():
         sv.wait(hs[-1])
     assert e.value.status == L.HG_ERR_CANCELLED
     sv.close()
+
+
+def test_dense_and_dia_problems_in_one_stream():
+    """Requests on dense-storage problems (the MFMA path) and on DIA problems share
+    one server; each result equals the same request evaluated alone."""
+    import paper_2304_06200_amd as hg
+    from workloads import make_config
+    reqs = _stream(6, seed=8)
+    dense_p = [make_config("gate3", d_t=4, N=2, random_amps=True, seed=s) for s in (1, 2)]
+    dense_prob = hg.Problem(context(), dense_p[0].H0, dense_p[0].Hk, dense_p[0].omega, dense=True)
+    sv = hg.Server(context(), hbm_budget_bytes=4 << 30, max_inflight=4)
+    log("[case] serving: 6 DIA requests and 2 dense-storage gate requests")
+    hs = [sv.submit(_problem(p), *_dev(p), p.dt, **_kw(p, "c64")) for p in reqs[:3]]
+    hs += [sv.submit(dense_prob, *_dev(p), p.dt, **_kw(p, "c64")) for p in dense_p]
+    hs += [sv.submit(_problem(p), *_dev(p), p.dt, **_kw(p, "c64")) for p in reqs[3:]]
+    out = [sv.wait(h) for h in hs]
+    sv.close()
+    order = [(p, _problem(p)) for p in reqs[:3]] + [(p, dense_prob) for p in dense_p] + \
+            [(p, _problem(p)) for p in reqs[3:]]
+    for (p, prob), (r, lat, q) in zip(order, out):
+        alone = hg.evaluate(prob, *_dev(p), p.dt, **_kw(p, "c64"))
+        assert r.cost[0] == alone.cost[0], p.name
+        assert np.array_equal(r.grad.cpu().numpy(), alone.grad.cpu().numpy()), p.name
