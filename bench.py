@@ -194,7 +194,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the evaluation is a "
-              f"single-GPU path; see DESIGN.md for how it would shard.", file=sys.stderr)
+              f"single-GPU path (sharding over state columns and evaluations is not built).",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
