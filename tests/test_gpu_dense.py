@@ -74,9 +74,12 @@ def test_dense_random_operators(seed, d, S, K, N, w_int):
             assert rel(r.integrated_infidelity[0], float(ref["integrated_infidelity"])) <= TOL[dtype]
 
 
-@pytest.mark.parametrize("d_t,N,random_amps", [(3, 2, True), (4, 4, True), (8, 1, False)])
+@pytest.mark.parametrize("d_t,N,random_amps", [(3, 2, True), (4, 4, True), (8, 1, False),
+                                                 (10, 1, False)])
 def test_dense_gate_full_basis(d_t, N, random_amps):
-    """Three-transmon Hadamard gate with S = d states; d_t = 8 is d = S = 512."""
+    """Three-transmon Hadamard gate with S = d states; d_t = 8 is d = S = 512 (the
+    bench size), d_t = 10 is d = S = 1000 (padded to 1024: 16 row tiles with a
+    ragged edge, 50 scaling steps of degree 16)."""
     p = make_config("gate3", d_t=d_t, N=N, random_amps=random_amps)
     log(f"[case] dense gate3 d_t={d_t} d={p.dim} S={p.n_states} N={N}")
     ref = _oracle(p)
