@@ -123,83 +123,82 @@ __global__ void __launch_bounds__(kTPB) k_term(TermArgs<R> a) {
 
   constexpr int AQ = kBM * RV / kTPB;  // 16-byte A vectors per thread and slab
   constexpr int XQ = kBN * RV / kTPB;  // 16-byte X vectors per thread and slab
-  uint4 ra[AQ], rx[XQ];  // the next slab, in flight while this one is computed
-  auto gload = [&](int t) {
-    const R* A;
-    const R* X;
-    int k0;
-    if (t < nk1) {
-      A = matb;
-      X = xb + (size_t)c0 * Mp;
-      k0 = t * BK;
-    } else {
-      A = a.emat + (size_t)b * a.emat_b + (size_t)(g - 1) * Mp * Mp;
-      X = xb + (size_t)cg * Mp;
-      k0 = (t - nk1) * BK;
-    }
-#pragma unroll
-    for (int q = 0; q < AQ; ++q) {
-      const int f = tid + kTPB * q, row = f / RV, cv = f % RV;
-      ra[q] = *reinterpret_cast<const uint4*>(A + (size_t)(i0 + row) * Mp + k0 + cv * VE);
-    }
-#pragma unroll
-    for (int q = 0; q < XQ; ++q) {
-      const int f = tid + kTPB * q, col = f / RV, cv = f % RV;
-      rx[q] = *reinterpret_cast<const uint4*>(X + (size_t)col * Mp + k0 + cv * VE);
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < AQ; ++q) {
-      const int f = tid + kTPB * q, row = f / RV, cv = f % RV;
-      *reinterpret_cast<uint4*>(&As[buf][row * LS + cv * VE]) = ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < XQ; ++q) {
-      const int f = tid + kTPB * q, col = f / RV, cv = f % RV;
-      *reinterpret_cast<uint4*>(&Xs[buf][col * LS + cv * VE]) = rx[q];
-    }
-  };
-
   v4 acc[WM][WN];
 #pragma unroll
   for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
     for (int ni = 0; ni < WN; ++ni) acc[mi][ni] = v4{0, 0, 0, 0};
 
-  auto compute = [&](int buf) {
-    const R* Ab = As[buf];
-    const R* Xb = Xs[buf];
-    // Within a chunk of 16 k, MFMA step q takes k = kc + 4*lg + q from lane
-    // group lg: each lane reads its four k of a row in one 16-byte load, and A
-    // and X use the same permutation of k, so the sum over k is unchanged.
+  // Iteration t loads slab t+1 into registers, computes slab t from LDS
+  // buffer t&1, then stores slab t+1 to the other buffer (t = -1 only loads
+  // and stores slab 0).  The staging registers are named variables: as a
+  // small array the compiler placed them in spare LDS, which made every slab
+  // wait for its global loads before the compute instead of after it.
+  static_assert(AQ == 4 && XQ == 2, "register staging is written for 128 x 64 tiles");
+  uint4 ra0, ra1, ra2, ra3, rx0, rx1;
+  for (int t = -1; t < nk; ++t) {
+    const int tn = t + 1;
+    if (tn < nk) {
+      const bool seg1 = tn < nk1;
+      const R* A = seg1 ? matb : a.emat + (size_t)b * a.emat_b + (size_t)(g - 1) * Mp * Mp;
+      const R* X = xb + (size_t)(seg1 ? c0 : cg) * Mp;
+      const int k0 = (seg1 ? tn : tn - nk1) * BK;
+      auto ga = [&](int q) {
+        const int f = tid + kTPB * q, row = f / RV, cv = f % RV;
+        return *reinterpret_cast<const uint4*>(A + (size_t)(i0 + row) * Mp + k0 + cv * VE);
+      };
+      auto gx = [&](int q) {
+        const int f = tid + kTPB * q, col = f / RV, cv = f % RV;
+        return *reinterpret_cast<const uint4*>(X + (size_t)col * Mp + k0 + cv * VE);
+      };
+      ra0 = ga(0);
+      ra1 = ga(1);
+      ra2 = ga(2);
+      ra3 = ga(3);
+      rx0 = gx(0);
+      rx1 = gx(1);
+    }
+    if (t >= 0) {
+      const R* Ab = As[t & 1];
+      const R* Xb = Xs[t & 1];
+      // Within a chunk of 16 k, MFMA step q takes k = kc + 4*lg + q from lane
+      // group lg: each lane reads its four k of a row in one 16-byte load, and
+      // A and X use the same permutation of k, so the sum over k is unchanged.
 #pragma unroll
-    for (int kc = 0; kc < BK; kc += 16) {
-      R av[WM][4], xv[WN][4];
-#pragma unroll
-      for (int mi = 0; mi < WM; ++mi)
-        ld4(Ab + (wm * 16 * WM + mi * 16 + lr) * LS + kc + 4 * lg, av[mi]);
-#pragma unroll
-      for (int ni = 0; ni < WN; ++ni)
-        ld4(Xb + (wn * 16 * WN + ni * 16 + lr) * LS + kc + 4 * lg, xv[ni]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int kc = 0; kc < BK; kc += 16) {
+        R av[WM][4], xv[WN][4];
 #pragma unroll
         for (int mi = 0; mi < WM; ++mi)
+          ld4(Ab + (wm * 16 * WM + mi * 16 + lr) * LS + kc + 4 * lg, av[mi]);
 #pragma unroll
-          for (int ni = 0; ni < WN; ++ni) acc[mi][ni] = M::mma(av[mi][q], xv[ni][q], acc[mi][ni]);
+        for (int ni = 0; ni < WN; ++ni)
+          ld4(Xb + (wn * 16 * WN + ni * 16 + lr) * LS + kc + 4 * lg, xv[ni]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int mi = 0; mi < WM; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < WN; ++ni)
+              acc[mi][ni] = M::mma(av[mi][q], xv[ni][q], acc[mi][ni]);
+      }
     }
-  };
-  // slab t is computed from LDS buffer t&1 while slab t+1 loads into
-  // registers; it is stored to the other buffer after the compute.  (A second
-  // register stage, two slabs ahead, measured slower.)
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int t = 0; t < nk; ++t) {
-    if (t + 1 < nk) gload(t + 1);
-    compute(t & 1);
-    if (t + 1 < nk) sstore((t + 1) & 1);
+    if (tn < nk) {
+      const int buf = tn & 1;
+      auto sa = [&](int q, uint4 v) {
+        const int f = tid + kTPB * q, row = f / RV, cv = f % RV;
+        *reinterpret_cast<uint4*>(&As[buf][row * LS + cv * VE]) = v;
+      };
+      auto sx = [&](int q, uint4 v) {
+        const int f = tid + kTPB * q, col = f / RV, cv = f % RV;
+        *reinterpret_cast<uint4*>(&Xs[buf][col * LS + cv * VE]) = v;
+      };
+      sa(0, ra0);
+      sa(1, ra1);
+      sa(2, ra2);
+      sa(3, ra3);
+      sx(0, rx0);
+      sx(1, rx1);
+    }
     __syncthreads();
   }
 
