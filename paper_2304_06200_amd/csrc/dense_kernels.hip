@@ -134,8 +134,8 @@ __global__ void __launch_bounds__(kTPB) k_term(TermArgs<R> a) {
   // and stores slab 0).  The staging registers are named variables: as a
   // small array the compiler placed them in spare LDS, which made every slab
   // wait for its global loads before the compute instead of after it.
-  static_assert(AQ == 4 && XQ == 2, "register staging is written for 128 x 64 tiles");
-  uint4 ra0, ra1, ra2, ra3, rx0, rx1;
+  static_assert(AQ == 4 && (XQ == 2 || XQ == 4), "staging is written for 128-row tiles");
+  uint4 ra0, ra1, ra2, ra3, rx0, rx1, rx2, rx3;
   for (int t = -1; t < nk; ++t) {
     const int tn = t + 1;
     if (tn < nk) {
@@ -157,6 +157,10 @@ __global__ void __launch_bounds__(kTPB) k_term(TermArgs<R> a) {
       ra3 = ga(3);
       rx0 = gx(0);
       rx1 = gx(1);
+      if constexpr (XQ == 4) {
+        rx2 = gx(2);
+        rx3 = gx(3);
+      }
     }
     if (t >= 0) {
       const R* Ab = As[t & 1];
@@ -198,6 +202,10 @@ __global__ void __launch_bounds__(kTPB) k_term(TermArgs<R> a) {
       sa(3, ra3);
       sx(0, rx0);
       sx(1, rx1);
+      if constexpr (XQ == 4) {
+        sx(2, rx2);
+        sx(3, rx3);
+      }
     }
     __syncthreads();
   }
@@ -580,10 +588,12 @@ hipError_t taylor(const DenseShape& sh, const Rot<R>& r, int G, int aux, R sgn, 
   a.N = sh.N;
   a.msch = msch;
   a.ssch = ssch;
-  // 128 x 64 tiles, measured fastest: 128 x 128 loads a third fewer operand
-  // bytes per flop but halves the workgroups; 64 x 64 fits four workgroups per
-  // CU but does half the MFMA work per LDS read and per barrier
-  constexpr int WN = 2, WM = 4;
+  // 128-row tiles; complex64 takes 128 columns when the padded state count
+  // allows (a third fewer operand bytes per flop, measured +2..4%), else 64.
+  // complex128 keeps 64 columns (at 128 its accumulators leave one wavefront
+  // per SIMD).  64 x 64 tiles measured far slower.
+  constexpr int WM = 4;
+  const int WN = (sizeof(R) == 4 && sh.Sp % 128 == 0) ? 4 : 2;
   const dim3 grid((unsigned)(G * sh.Sp / (32 * WN)), (unsigned)(Mp / (32 * WM)), (unsigned)sh.B);
   const size_t cnt = (size_t)G * sh.Sp * Mp;
   for (int rep = 1; rep <= smax; ++rep) {
@@ -595,7 +605,13 @@ hipError_t taylor(const DenseShape& sh, const Rot<R>& r, int G, int aux, R sgn, 
       a.accout = r.A;
       a.tout = r.T[j & 1];
       a.scale = sgn / (R)j;
-      hipLaunchKernelGGL((k_term<R, WM, WN>), grid, dim3(kTPB), 0, st, a);
+      if constexpr (sizeof(R) == 4) {
+        if (WN == 4) {
+          hipLaunchKernelGGL((k_term<R, WM, 4>), grid, dim3(kTPB), 0, st, a);
+          continue;
+        }
+      }
+      hipLaunchKernelGGL((k_term<R, WM, 2>), grid, dim3(kTPB), 0, st, a);
     }
     hipLaunchKernelGGL(k_dense_copy<R>, dim3(stride_blocks(cnt), sh.B), dim3(256), 0, st,
                        (const R*)r.A, r.P, r.stride, r.stride, cnt, ssch, sh.N, n, rep);
