@@ -384,6 +384,7 @@ static DenseShape dense_shape(const hg_problem* p, int B, int N, int S, bool c12
   sh.Sp = (S + 63) / 64 * 64;
   sh.B = B;
   sh.c128 = c128;
+  sh.num_cu = p->ctx->num_cu;
   return sh;
 }
 

@@ -589,11 +589,13 @@ hipError_t taylor(const DenseShape& sh, const Rot<R>& r, int G, int aux, R sgn, 
   a.msch = msch;
   a.ssch = ssch;
   // 128-row tiles; complex64 takes 128 columns when the padded state count
-  // allows (a third fewer operand bytes per flop, measured +2..4%), else 64.
-  // complex128 keeps 64 columns (at 128 its accumulators leave one wavefront
-  // per SIMD).  64 x 64 tiles measured far slower.
+  // allows (a third fewer operand bytes per flop, measured +2..4%) and the
+  // launch still has two workgroups per CU, else 64.  complex128 keeps 64
+  // columns (at 128 its accumulators leave one wavefront per SIMD).  64 x 64
+  // tiles measured far slower.
   constexpr int WM = 4;
-  const int WN = (sizeof(R) == 4 && sh.Sp % 128 == 0) ? 4 : 2;
+  const size_t wg128 = (size_t)G * (sh.Sp / 128) * (Mp / (32 * WM)) * sh.B;
+  const int WN = (sizeof(R) == 4 && sh.Sp % 128 == 0 && wg128 >= 2 * (size_t)sh.num_cu) ? 4 : 2;
   const dim3 grid((unsigned)(G * sh.Sp / (32 * WN)), (unsigned)(Mp / (32 * WM)), (unsigned)sh.B);
   const size_t cnt = (size_t)G * sh.Sp * Mp;
   for (int rep = 1; rep <= smax; ++rep) {

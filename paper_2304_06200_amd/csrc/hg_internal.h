@@ -126,6 +126,7 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
 struct DenseShape {
   int d, dp, K, N, S, Sp, B;  // Sp = S rounded up to 64
   bool c128;
+  int num_cu;                 // compute units of the device (tile choice)
 };
 struct DenseBuffers {
   const double* u;
