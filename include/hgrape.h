@@ -179,7 +179,9 @@ typedef struct {
   int64_t sum_mu;            /* sum over steps of m_n s_n */
   double max_theta;          /* max_n ||A_n||_1 */
   double max_bound;          /* max_n E_A(m_n, s_n) (0 with a frozen schedule) */
-  double drift;              /* reconstruction drift: max_h ||psi_0^h(rebuilt) - psi_0^h|| */
+  double drift;              /* reconstruction drift: max_h ||psi_0^h(rebuilt) - psi_0^h||;
+                                in CHECKPOINT mode only the rounding of psi_0 to the
+                                working precision (0 for HG_C128) */
   double ms_forward;         /* with HG_FLAG_TIMING: forward-sweep kernel time (whole batch) */
   double ms_backward;        /* with HG_FLAG_TIMING: backward-sweep kernel time (whole batch) */
 } hg_result;

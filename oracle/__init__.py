@@ -18,8 +18,10 @@ performance of GRAPE" (arXiv:2304.06200) that it follows.
 
 Parity status: grape and taylor are pinned by closed forms, invariants, finite
 differences and high-precision references (tests/test_oracle_*.py).  The
-planner formula is pinned by closed forms of its s=1 and s=2 special cases and
-by the empirical bound property; *which* (m, s) the authors obtained for any
+planner formula is pinned by the special cases App. C writes out (the rounding
+part at m = 0 and m = 1, eq. c17, composed over s = 1 and s = 2, eqs. s1 and
+C22), by the tight truncation bound of a 1x1 operator, by a 50-digit tail sum
+and by the empirical bound property; *which* (m, s) the authors obtained for any
 given norm is parity unpinned (the paper prints no such values).
 """
 from . import grape, planner, taylor  # noqa: F401

@@ -877,7 +877,9 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   }
   }
 
-  // drift of the rebuilt initial state (zero by construction in the checkpoint variant)
+  // drift of the rebuilt initial state; in the checkpoint variant psi_0 is never
+  // rebuilt, so this is only its rounding to the working precision when it was
+  // stored as checkpoint 0 (zero in complex128)
   double dv[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r)

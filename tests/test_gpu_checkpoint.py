@@ -67,3 +67,28 @@ def test_footprint_state_memory():
     c = fp(5000, L.HG_MODE_CHECKPOINT, 100)
     extra = (50 + 100) * d * S * 8
     assert abs((c - b) - extra) <= 2 * 256
+
+
+def test_checkpoint_drift_is_rounding_of_psi0():
+    """In the checkpoint variant the states are never rebuilt, so the reported
+    drift is only the rounding of psi_0 to the working precision when it is
+    stored as checkpoint 0: exactly 0 in complex128 and ||fl32(psi_0) - psi_0||
+    in complex64 (a random normalised psi_0 is not representable in FP32)."""
+    import dataclasses
+    p = make_config("cfg2", N=60, d_c=10)
+    rng = np.random.default_rng(61)
+    psi0 = rng.normal(size=p.psi0.shape) + 1j * rng.normal(size=p.psi0.shape)
+    psi0 /= np.linalg.norm(psi0, axis=1, keepdims=True)
+    q = dataclasses.replace(p, psi0=psi0)
+    ref = _oracle(q)
+    log("[case] checkpoint drift, random psi0, cfg2 d_c=10 N=60")
+    r128 = run(q, "c128", mode="checkpoint", ckpt_every=7)
+    assert_parity(r128, ref, "c128", label="ckpt-rand-psi0")
+    assert r128.drift[0] == 0.0
+    r64 = run(q, "c64", mode="checkpoint", ckpt_every=7)
+    assert_parity(r64, ref, "c64", label="ckpt-rand-psi0")
+    expect = max(np.linalg.norm(psi0[h].astype(np.complex64).astype(np.complex128) - psi0[h])
+                 for h in range(psi0.shape[0]))
+    log(f"[case] c64 checkpoint drift {r64.drift[0]:.3e}, FP32 rounding of psi0 {expect:.3e}")
+    assert 0.0 < r64.drift[0] <= 1e-7
+    assert r64.drift[0] == pytest.approx(expect, rel=1e-6)

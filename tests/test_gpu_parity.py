@@ -112,3 +112,28 @@ def test_finite_differences_of_gpu_cost():
         cm = run(p, "c128", prob=prob, schedule=sched, batch_u=um).cost[0]
         fd = (cp - cm) / (2 * h)
         assert abs(fd - g[k, n]) <= 1e-7 * max(1.0, np.max(np.abs(g))), (k, n, fd, g[k, n])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_cfg3_fidelity_dominated_full_dimension(dtype):
+    """d = 1600, 16 states, N = 24, no penalty, and targets that the amplitudes
+    nearly reach (|g| ~ 0.97): the gradient is then carried by the fidelity
+    co-state at full strength, unlike the Haar-target run where |g| ~ 0.01.
+    The targets are the oracle's Taylor-discretised evolution under a second
+    seeded amplitude set within 2 pi * 0.01 GHz of u; the reference is the
+    discretised oracle on the oracle planner's schedule, frozen on both sides."""
+    import dataclasses
+    from oracle import taylor
+    p = make_config("cfg3", N=24)
+    sched = oracle_schedule(p)
+    u2 = p.u + 2 * np.pi * 0.01 * np.random.default_rng(303).uniform(-1, 1, p.u.shape)
+    psi = p.psi0.T.copy()
+    for n in range(p.n_steps):
+        H = p.H0 + sum(u2[k, n] * p.Hk[k] for k in range(p.n_ctrl))
+        psi = taylor.taylor_action(-1j * p.dt * H, psi, int(sched[0, n]), int(sched[1, n]))
+    q = dataclasses.replace(p, targets=psi.T.copy(), omega=None, w_pen=0.0)
+    ref = taylor.hg_discrete(q.H0, q.Hk, q.u, q.dt, q.psi0, q.targets, sched, omega=None,
+                             w_fid=1.0, w_pen=0.0)
+    log(f"[case] cfg3 fidelity-dominated d=1600 N=24 S=16 {dtype} |g|={abs(ref['overlap']):.4f}")
+    assert abs(ref["overlap"]) > 0.9
+    assert_parity(run(q, dtype, schedule=sched), ref, dtype, label="cfg3-fid")

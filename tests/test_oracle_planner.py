@@ -5,8 +5,9 @@ matrix, where the triangle-inequality bound is tight to first order (so a
 wrong index, a dropped factor s or a wrong scaled norm shows up as a ratio far
 from 1); its tail sum against a 50-digit mpmath evaluation of e^x minus the
 partial sum; the stable rewrite of (alpha+beta)^s - alpha^s against the literal
-difference at 50 digits; and the selection rule against brute-force
-minimality.  Which (m, s) the authors obtained for a given norm is parity
+difference at 50 digits; the rounding part against the special cases the paper
+writes out (m = 0 and m = 1 of App. C.2, s = 1 and s = 2 of App. C.3); and the
+selection rule against brute-force minimality.  Which (m, s) the authors obtained for a given norm is parity
 unpinned: the paper prints no such values.
 """
 import math
@@ -118,3 +119,57 @@ def test_unreachable_tolerance():
         planner.select(10.0, 9, 1e-8, u=planner.U_FP32)
     with pytest.raises(ValueError):
         planner.select(float("nan"), 9, 1e-12)
+
+
+# ---- the rounding part against the special cases the paper writes out ------
+# App. C.2 spells out the per-component rounding bound for m = 0 (gamma_2) and
+# for m = 1 (gamma_3 + gamma_{sigma+5} ||B||_1 after summing over the row, eq.
+# c17); App. C.3 spells out the bound after s = 1 (beta, eq. s1) and s = 2
+# (beta (beta + alpha) + beta alpha, eq. C22).  These are typed here from those
+# printed forms, not from the general index k(sigma'+2)+m+2 of eq. B23, so a
+# wrong index or a wrong composition over s in the oracle (or in the C++
+# planner, checked the same way) fails.  A large unit roundoff keeps the
+# rounding part well above the FP64 noise of the truncation part.
+_U_BIG = mp.mpf(2) ** -20
+
+
+def _gamma_printed(n):
+    up = 2 * mp.sqrt(2) * _U_BIG / (1 - 2 * _U_BIG)
+    return n * up / (1 - n * up)
+
+
+def _printed_case(m, s, theta, sigma):
+    x = mp.mpf(theta) / s
+    if m == 0:
+        beta = _gamma_printed(2)
+    else:
+        beta = _gamma_printed(3) + _gamma_printed(sigma + 5) * x
+    R = _tail_mp(x, m)
+    alpha = 1 + R
+    rnd = beta if s == 1 else beta * (beta + alpha) + beta * alpha
+    sR = s * R
+    trunc = sR * (1 - sR ** s) / (1 - sR)
+    return trunc, rnd
+
+
+PRINTED_CASES = [(0, 1, 0.02, 3), (0, 2, 0.02, 5), (0, 1, 0.3, 9),
+                 (1, 1, 0.05, 3), (1, 2, 0.05, 3), (1, 1, 0.2, 9), (1, 2, 0.4, 5), (1, 2, 0.1, 13)]
+
+
+@pytest.mark.parametrize("m,s,theta,sigma", PRINTED_CASES)
+def test_rounding_part_printed_special_cases(m, s, theta, sigma):
+    trunc, rnd = _printed_case(m, s, theta, sigma)
+    got = planner.error_bound(theta, m, s, sigma, u=float(_U_BIG))
+    # the rounding part is ~1e-3..1e-2 of the total here, so comparing it alone
+    # keeps FP64 noise of the total far below the tolerance
+    assert got - float(trunc) == pytest.approx(float(rnd), rel=1e-9)
+    assert got == pytest.approx(float(trunc + rnd), rel=1e-13)
+
+
+@pytest.mark.parametrize("m,s,theta,sigma", [c for c in PRINTED_CASES if c[0] >= 1])
+def test_library_rounding_part_printed_special_cases(m, s, theta, sigma):
+    """The C++ planner's bound (hg_error_bound, m >= 1) against the same printed cases."""
+    from paper_2304_06200_amd import _lib
+    trunc, rnd = _printed_case(m, s, theta, sigma)
+    got = _lib.hg_error_bound(theta, m, s, sigma, float(_U_BIG))
+    assert got - float(trunc) == pytest.approx(float(rnd), rel=1e-9)
