@@ -61,6 +61,11 @@ typedef enum {
 
 typedef enum { HG_C64 = 0, HG_C128 = 1 } hg_dtype;  /* arithmetic of the Taylor products */
 typedef enum { HG_MODE_RECONSTRUCT = 0, HG_MODE_CHECKPOINT = 1 } hg_mode;
+/* Choice of (m, s) per step under the bound E_A(m, s) <= tau of App. C:
+ * the paper's rule (smallest s, then smallest m; Sec. III.B) or the fewest
+ * products mu = m s (ties: smaller s), the alternative Sec. III.B mentions and
+ * sets aside because the minimisation costs more than it saves there. */
+typedef enum { HG_PLAN_SMALLEST_S = 0, HG_PLAN_MIN_MU = 1 } hg_plan_rule_t;
 
 /* A host CSR matrix of complex128 values (dim x dim). */
 typedef struct {
@@ -73,7 +78,9 @@ typedef struct {
 typedef struct hg_ctx hg_ctx;
 typedef struct hg_problem hg_problem;
 
-/* Create a context bound to HIP device `device_ordinal`. */
+/* Create a context bound to HIP device `device_ordinal`.  Also raises the
+ * release threshold of the device's default memory pool (evaluation
+ * workspaces then stay pooled between calls). */
 hg_status hg_create(int device_ordinal, hg_ctx** out);
 hg_status hg_destroy(hg_ctx* ctx);
 const char* hg_status_string(hg_status s);
@@ -132,6 +139,10 @@ hg_status hg_problem_info(const hg_problem* p, int64_t* dim, int32_t* n_ctrl,
 hg_status hg_plan(const double* theta, int64_t n, int32_t sigma, double tau, double u,
                   int32_t* m_out, int32_t* s_out);
 
+/* hg_plan with a choice of rule (hg_plan_rule_t); HG_PLAN_SMALLEST_S is hg_plan. */
+hg_status hg_plan_rule(const double* theta, int64_t n, int32_t sigma, double tau, double u,
+                       int32_t rule, int32_t* m_out, int32_t* s_out);
+
 /* Error bound E_A(m, s) of App. C at ||A||_1 = theta (host, FP64). */
 double hg_error_bound(double theta, int32_t m, int32_t s, int32_t sigma, double u);
 
@@ -166,6 +177,7 @@ typedef struct {
                                 (the planner is skipped; norms are still computed) */
   int32_t flags;             /* bit 0 (HG_FLAG_TIMING): time the sweep kernels with
                                 HIP events on `stream`, reported in hg_result */
+  int32_t rule;              /* hg_plan_rule_t of the planner (0 = the paper's) */
 } hg_eval_desc;
 
 #define HG_FLAG_TIMING 1
@@ -188,10 +200,16 @@ typedef struct {
 
 /* Evaluate cost and gradient for B amplitude sets.  results: host [B];
  * grad: device [B][n_ctrl][N] FP64 (may be NULL for cost only).  Work is
- * enqueued on `stream`; the call returns after the stream has finished it
- * (the planner needs the norms on the host mid-way), so results and grad
- * are valid on return.  One workgroup holds one state column's term vectors
- * in LDS: UNSUPPORTED when they do not fit (e.g. complex128 above 2048 rows).
+ * enqueued on `stream`; the call returns after the stream has finished it,
+ * so results and grad are valid on return.  This is synchronous on purpose:
+ * the (m, s) schedule is chosen on the host by the FP64 planner from the
+ * norms the device computed, so that every decision equals the reference
+ * rule's, and the call waits for them mid-way.  The workspace comes
+ * stream-ordered from the device's default memory pool (freed blocks stay in
+ * the pool, see hg_create) and the host staging is pinned memory kept per
+ * calling thread, so repeated calls allocate nothing new.  One workgroup holds
+ * one state column's term vectors in LDS: UNSUPPORTED when they do not fit
+ * (e.g. complex128 above 2048 rows).
  * Errors: INVALID_ARG, NONFINITE, TOLERANCE_UNREACHABLE, UNSUPPORTED,
  * OUT_OF_MEMORY, DEVICE. */
 hg_status hg_eval(hg_problem* p, const hg_eval_desc* desc, hg_result* results,
@@ -200,6 +218,12 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* desc, hg_result* results,
 /* Device memory the library would allocate for one hg_eval call with this
  * shape (workspace only; caller buffers excluded).  Used for admission. */
 hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* desc, size_t* bytes);
+
+/* High-water mark of device memory handed out by the device's default pool,
+ * which holds every evaluation workspace (bytes; operators and caller buffers
+ * are not in it).  reset != 0 restarts the mark at the current use.  This is
+ * the measured peak of hg_eval's own device memory (Table I's comparison). */
+hg_status hg_mem_pool_peak(hg_ctx* ctx, int32_t reset, size_t* used_high);
 
 /* ---------------------------------------------------------------- serving ----
  * A server admits cost+gradient requests (any problem, any shape) onto the
@@ -216,11 +240,18 @@ typedef struct hg_server hg_server;
 
 hg_status hg_server_create(hg_ctx* ctx, size_t hbm_budget_bytes, int32_t max_inflight,
                            hg_server** out);
-/* Queue a request.  Errors at submit: INVALID_ARG (and the other hg_eval
- * argument checks), OUT_OF_MEMORY (footprint larger than the whole budget),
- * BUSY (queue full or server shutting down).  Writes the request id. */
+/* Queue a request.  The request's device work is ordered after everything
+ * queued on `after_stream` (a hipStream_t of the caller, NULL = the null
+ * stream) up to this call: the inputs may still be in flight there (e.g.
+ * produced by the kernel just launched), the server waits for them on the
+ * device.  grad is written on a worker stream and is complete when
+ * hg_server_wait returns.  Errors at submit: INVALID_ARG (and the other
+ * hg_eval argument checks), OUT_OF_MEMORY (footprint larger than the whole
+ * budget), BUSY (queue full or server shutting down), DEVICE.  Writes the
+ * request id. */
 hg_status hg_server_submit(hg_server* sv, hg_problem* p, const hg_eval_desc* desc,
-                           hg_result* results, double* grad, uint64_t* req_id);
+                           hg_result* results, double* grad, void* after_stream,
+                           uint64_t* req_id);
 /* done = 1 once the request finished (successfully or not). */
 hg_status hg_server_poll(hg_server* sv, uint64_t req_id, int32_t* done);
 /* Block until the request finished; returns its hg_eval status (CANCELLED if it

@@ -119,3 +119,29 @@ def one_norm(dense_matrix) -> float:
     anti-Hermitian A = -i dt H), App. C.1."""
     import numpy as np
     return float(np.max(np.sum(np.abs(np.asarray(dense_matrix)), axis=0)))
+
+
+def select_min_mu(theta: float, sigma: int, tau: float, u: float = U_FP64,
+                  m_max: int = M_MAX) -> Tuple[int, int]:
+    """(m, s) with the fewest products mu = m s under the same bound E_A <= tau
+    (the alternative Sec. III.B sets aside after eq. accuracy inequality because
+    the minimisation costs more than it saves there); ties go to the smaller s.
+
+    For each s the smallest feasible m is the cheapest, so the search takes,
+    for s = 1, 2, ..., that m, and stops once s alone exceeds the best mu found
+    (every larger s costs at least s products).  Raises ValueError when no
+    (m <= m_max, s) satisfies the bound."""
+    if not (theta >= 0.0) or math.isinf(theta):
+        raise ValueError(f"invalid norm {theta!r}")
+    best = None
+    for s in range(1, s_limit(tau, u) + 1):
+        if best is not None and s > best[0] * best[1]:
+            break
+        for m in range(1, m_max + 1):
+            if error_bound(theta, m, s, sigma, u) <= tau:
+                if best is None or m * s < best[0] * best[1]:
+                    best = (m, s)
+                break
+    if best is None:
+        raise ValueError(f"tolerance {tau:g} unreachable at norm {theta:g}")
+    return best

@@ -29,6 +29,7 @@ HG_C128 = 1
 HG_FLAG_TIMING = 1
 HG_MODE_RECONSTRUCT = 0
 HG_MODE_CHECKPOINT = 1
+HG_PLAN_SMALLEST_S, HG_PLAN_MIN_MU = 0, 1
 
 
 class HGError(RuntimeError):
@@ -57,7 +58,7 @@ class hg_eval_desc(C.Structure):
                 ("targets", C.c_void_p), ("w_fid", C.c_double), ("w_pen", C.c_double),
                 ("w_int", C.c_double), ("tau", C.c_double), ("dtype", C.c_int), ("mode", C.c_int),
                 ("ckpt_every", C.c_int32), ("renorm_every", C.c_int32),
-                ("schedule", C.POINTER(C.c_int32)), ("flags", C.c_int32)]
+                ("schedule", C.POINTER(C.c_int32)), ("flags", C.c_int32), ("rule", C.c_int32)]
 
 
 class hg_result(C.Structure):
@@ -92,12 +93,16 @@ def _load():
         "hg_plan": (C.c_int, [C.POINTER(C.c_double), C.c_int64, C.c_int32, C.c_double,
                               C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "hg_error_bound": (C.c_double, [C.c_double, C.c_int32, C.c_int32, C.c_int32, C.c_double]),
+        "hg_plan_rule": (C.c_int, [C.POINTER(C.c_double), C.c_int64, C.c_int32, C.c_double,
+                                   C.c_double, C.c_int32, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32)]),
         "hg_step_norms": (C.c_int, [P, P, C.c_int32, C.c_int32, C.c_double, P, P]),
         "hg_eval": (C.c_int, [P, C.POINTER(hg_eval_desc), C.POINTER(hg_result), P, P]),
         "hg_eval_footprint": (C.c_int, [P, C.POINTER(hg_eval_desc), C.POINTER(C.c_size_t)]),
         "hg_server_create": (C.c_int, [P, C.c_size_t, C.c_int32, C.POINTER(P)]),
         "hg_server_submit": (C.c_int, [P, P, C.POINTER(hg_eval_desc), C.POINTER(hg_result), P,
-                                       C.POINTER(C.c_uint64)]),
+                                       P, C.POINTER(C.c_uint64)]),
+        "hg_mem_pool_peak": (C.c_int, [P, C.c_int32, C.POINTER(C.c_size_t)]),
         "hg_server_poll": (C.c_int, [P, C.c_uint64, C.POINTER(C.c_int32)]),
         "hg_server_wait": (C.c_int, [P, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "hg_server_cancel": (C.c_int, [P, C.c_uint64]),
@@ -114,8 +119,8 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("hg_create", "hg_destroy", "hg_status_string", "hg_last_error", "hg_version",
-            "hg_problem_create", "hg_problem_create_dense", "hg_problem_destroy", "hg_problem_info", "hg_plan",
-            "hg_error_bound", "hg_step_norms", "hg_eval", "hg_eval_footprint",
+            "hg_problem_create", "hg_problem_create_dense", "hg_problem_destroy", "hg_problem_info", "hg_plan", "hg_plan_rule",
+            "hg_error_bound", "hg_step_norms", "hg_eval", "hg_eval_footprint", "hg_mem_pool_peak",
             "hg_server_create", "hg_server_submit", "hg_server_poll", "hg_server_wait",
             "hg_server_cancel", "hg_server_info", "hg_server_destroy")
 
@@ -189,6 +194,17 @@ def hg_plan(theta, sigma: int, tau: float, u: float):
     return m, s
 
 
+def hg_plan_rule(theta, sigma: int, tau: float, u: float, rule: int):
+    import numpy as np
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    m = np.zeros(th.size, dtype=np.int32)
+    s = np.zeros(th.size, dtype=np.int32)
+    _check(_lib.hg_plan_rule(th.ctypes.data_as(C.POINTER(C.c_double)), th.size, sigma, tau, u,
+                             rule, m.ctypes.data_as(C.POINTER(C.c_int32)),
+                             s.ctypes.data_as(C.POINTER(C.c_int32))), "hg_plan_rule")
+    return m, s
+
+
 def hg_error_bound(theta: float, m: int, s: int, sigma: int, u: float) -> float:
     return float(_lib.hg_error_bound(theta, m, s, sigma, u))
 
@@ -216,11 +232,18 @@ def hg_server_create(ctx: int, hbm_budget_bytes: int, max_inflight: int) -> int:
     return out.value
 
 
-def hg_server_submit(sv: int, p: int, desc: hg_eval_desc, results, grad_ptr) -> int:
+def hg_server_submit(sv: int, p: int, desc: hg_eval_desc, results, grad_ptr,
+                     after_stream) -> int:
     rid = C.c_uint64()
-    _check(_lib.hg_server_submit(sv, p, C.byref(desc), results, grad_ptr, C.byref(rid)),
-           "hg_server_submit")
+    _check(_lib.hg_server_submit(sv, p, C.byref(desc), results, grad_ptr, after_stream,
+                                 C.byref(rid)), "hg_server_submit")
     return int(rid.value)
+
+
+def hg_mem_pool_peak(ctx: int, reset: bool = False) -> int:
+    out = C.c_size_t()
+    _check(_lib.hg_mem_pool_peak(ctx, 1 if reset else 0, C.byref(out)), "hg_mem_pool_peak")
+    return int(out.value)
 
 
 def hg_server_poll(sv: int, req_id: int) -> bool:

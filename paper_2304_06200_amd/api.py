@@ -109,7 +109,7 @@ def _ptr(t) -> int:
 
 def make_desc(n_steps, n_batch, dt, u, n_states, psi0, targets, w_fid, w_pen, tau, dtype,
               renorm_every, schedule=None, mode=L.HG_MODE_RECONSTRUCT, ckpt_every=0, flags=0,
-              w_int=0.0):
+              w_int=0.0, rule=L.HG_PLAN_SMALLEST_S):
     d = L.hg_eval_desc()
     d.n_steps = n_steps
     d.n_batch = n_batch
@@ -128,14 +128,18 @@ def make_desc(n_steps, n_batch, dt, u, n_states, psi0, targets, w_fid, w_pen, ta
     d.renorm_every = renorm_every
     d.schedule = schedule
     d.flags = flags
+    d.rule = rule
     return d
+
+
+RULES = {"smallest_s": L.HG_PLAN_SMALLEST_S, "min_mu": L.HG_PLAN_MIN_MU}
 
 
 def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.0,
              w_pen: float = 0.0, w_int: float = 0.0, tau: float = 1e-12, dtype: str = "c128",
              renorm_every: Optional[int] = None, schedule: Optional[np.ndarray] = None,
              want_grad: bool = True, timing: bool = False, mode: str = "reconstruct",
-             ckpt_every: int = 0, stream=None) -> EvalResult:
+             ckpt_every: int = 0, stream=None, rule: str = "smallest_s") -> EvalResult:
     """Cost and gradient of B amplitude sets.
 
     u        torch float64 device tensor (K, N) or (B, K, N)
@@ -146,6 +150,7 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
     mode     "reconstruct" (HG inverse propagation) or "checkpoint" (psi stored
              every ckpt_every steps, segments re-propagated in the backward sweep)
     w_int    weight of the time-integrated infidelity C3 (0 = off)
+    rule     planner rule: "smallest_s" (the paper's) or "min_mu" (fewest products)
     """
     torch = _torch()
     if u.dim() == 2:
@@ -184,7 +189,7 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
     desc = make_desc(N, B, dt, _ptr(u) if K > 0 else None, S, _ptr(psi0), _ptr(targets),
                      w_fid, w_pen, tau, code, renorm_every, sched_p, mode=mcode,
                      ckpt_every=ckpt_every, flags=L.HG_FLAG_TIMING if timing else 0,
-                     w_int=w_int)
+                     w_int=w_int, rule=RULES[rule])
     grad = torch.empty((B, K, N), dtype=torch.float64, device=u.device) if want_grad and K > 0 else None
     res = (L.hg_result * B)()
     st = stream if stream is not None else torch.cuda.current_stream(u.device).cuda_stream
@@ -215,6 +220,15 @@ def step_norms(problem: Problem, u, dt: float, stream=None):
     return out
 
 
-def plan(theta: np.ndarray, sigma: int, tau: float, u: float = 2.0 ** -53):
+def mem_pool_peak(ctx: Context, reset: bool = False) -> int:
+    """Measured high-water mark (bytes) of the library's evaluation workspaces
+    on the context's device since the last reset; reset=True restarts it."""
+    return L.hg_mem_pool_peak(ctx.handle, reset)
+
+
+def plan(theta: np.ndarray, sigma: int, tau: float, u: float = 2.0 ** -53,
+         rule: str = "smallest_s"):
     """Host planner of the library (FP64): (m, s) arrays for the norms theta."""
-    return L.hg_plan(np.asarray(theta, dtype=np.float64), sigma, tau, u)
+    if rule == "smallest_s":
+        return L.hg_plan(np.asarray(theta, dtype=np.float64), sigma, tau, u)
+    return L.hg_plan_rule(np.asarray(theta, dtype=np.float64), sigma, tau, u, RULES[rule])

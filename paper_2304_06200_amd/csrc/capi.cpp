@@ -166,6 +166,12 @@ hg_status hg_create(int device_ordinal, hg_ctx** out) {
   c->num_cu = v;
   HG_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device_ordinal));
   c->lds_per_block = (size_t)v;
+  // evaluation workspaces come from the device's default pool (hipMallocAsync):
+  // keep freed blocks in the pool instead of returning them at every sync
+  hipMemPool_t pool;
+  HG_HIP(hipDeviceGetDefaultMemPool(&pool, device_ordinal));
+  uint64_t keep = UINT64_MAX;
+  HG_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
   *out = c.release();
   return HG_OK;
 }
@@ -326,16 +332,19 @@ double hg_error_bound(double theta, int32_t m, int32_t s, int32_t sigma, double 
 }
 
 static hg_status plan_impl(const double* theta, int64_t n, int32_t sigma, double tau, double u,
-                  int32_t* m_out, int32_t* s_out) {
+                           int32_t* m_out, int32_t* s_out, bool table = true,
+                           int rule = HG_PLAN_SMALLEST_S) {
   if (n < 0 || (n > 0 && (!theta || !m_out || !s_out)) || sigma < 1 || !(tau > 0.0) ||
       !(u > 0.0 && u < 0.25))
     return fail(HG_ERR_INVALID_ARG, "hg_plan: bad argument");
+  if (rule != HG_PLAN_SMALLEST_S && rule != HG_PLAN_MIN_MU)
+    return fail(HG_ERR_INVALID_ARG, "hg_plan: unknown rule");
   for (int64_t i = 0; i < n; ++i) {
     if (!std::isfinite(theta[i])) return fail(HG_ERR_NONFINITE, "norm " + std::to_string(i) + " is not finite");
     if (theta[i] < 0.0) return fail(HG_ERR_INVALID_ARG, "negative norm");
   }
   int64_t bad = -1;
-  const int rc = plan_steps(theta, n, sigma, tau, u, m_out, s_out, &bad);
+  const int rc = plan_steps(theta, n, sigma, tau, u, m_out, s_out, &bad, table, rule);
   if (rc == 2)
     return fail(HG_ERR_UNSUPPORTED, "step " + std::to_string(bad) + " (norm " +
                                         std::to_string(theta[bad]) + ") would need s > " +
@@ -442,6 +451,8 @@ static hg_status check_desc(const hg_problem* p, const hg_eval_desc* d) {
   if (d->mode == HG_MODE_CHECKPOINT && d->ckpt_every < 1)
     return fail(HG_ERR_INVALID_ARG, "checkpoint mode needs ckpt_every >= 1");
   if (d->renorm_every < 0) return fail(HG_ERR_INVALID_ARG, "renorm_every must be >= 0");
+  if (d->rule != HG_PLAN_SMALLEST_S && d->rule != HG_PLAN_MIN_MU)
+    return fail(HG_ERR_INVALID_ARG, "unknown planner rule");
   if ((p->n_ctrl > 0 && !d->u) || !d->psi0 || !d->targets)
     return fail(HG_ERR_INVALID_ARG, "NULL device array");
   if (p->dense && d->mode != HG_MODE_RECONSTRUCT)
@@ -459,53 +470,32 @@ hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* d, size_t* 
   return HG_OK;
 }
 
-static hg_status eval_impl(hg_problem* p, const hg_eval_desc* d, hg_result* results, double* grad,
-                  void* stream) {
-  hg_status st = check_desc(p, d);
-  if (st != HG_OK) return st;
-  if (!results) return fail(HG_ERR_INVALID_ARG, "results is NULL");
+// Bytes of host staging one evaluation needs: norms, state norms, schedule,
+// result scalars and drifts.
+static size_t host_stage_bytes(int B, int N, int S) {
+  return (size_t)B * N * 8 + (size_t)B * S * 8 + (size_t)2 * B * N * 4 + (size_t)B * 8 * 8 +
+         (size_t)B * S * 8;
+}
+
+// The evaluation proper, on a workspace `ws` laid out by layout() and a host
+// staging area `hbuf` of host_stage_bytes() (pinned or pageable).  `table`
+// lets the planner build and cache its threshold table; without it the planner
+// uses a cached table if there is one, else the direct search (same decisions).
+static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* results, double* grad,
+                           hipStream_t hs, const SweepShape& sh0, const Workspace& w, char* ws,
+                           char* hbuf, bool table) {
   const int B = d->n_batch, N = d->n_steps, S = d->n_states, K = p->n_ctrl;
   const bool c128 = d->dtype == HG_C128;
-  hipStream_t hs = (hipStream_t)stream;
-  HG_HIP(hipSetDevice(p->ctx->device));
-
-  SweepShape sh{};
-  std::string why;
-  if (!p->dense &&
-      !sweep_supported(p->ops, (int)p->dim, K, c128, p->ctx->lds_per_block, &sh, &why))
-    return fail(HG_ERR_UNSUPPORTED, why);
-  sh.n_steps = N;
-  sh.n_states = S;
-  sh.n_batch = B;
-
+  hg_status st = HG_OK;
+  SweepShape sh = sh0;
   const int ck = d->mode == HG_MODE_CHECKPOINT ? std::min(d->ckpt_every, N) : 0;
-  const Workspace w = layout(p, B, N, S, c128, ck, d->w_int != 0.0);
-  char* ws = nullptr;
-  if (hipMallocAsync((void**)&ws, w.total, hs) != hipSuccess)
-    return fail(HG_ERR_OUT_OF_MEMORY, "workspace of " + std::to_string(w.total) + " bytes");
-  struct Free {
-    char* p;
+  struct Drain {  // on an early return, copies into the staging area may still be queued
     hipStream_t s;
-    ~Free() {
-      if (p) (void)hipFreeAsync(p, s);
+    bool armed = true;
+    ~Drain() {
+      if (armed) (void)hipStreamSynchronize(s);
     }
-  } guard{ws, hs};
-
-  // host staging (pinned): norms, state norms, schedule, result scalars
-  const size_t hbytes = (size_t)B * N * 8 + (size_t)B * S * 8 + (size_t)2 * B * N * 4 +
-                        (size_t)B * 8 * 8 + (size_t)B * S * 8;
-  char* hbuf = nullptr;
-  HG_HIP(hipHostMalloc((void**)&hbuf, hbytes, hipHostMallocDefault));
-  struct HFree {  // on an early return, copies into it may still be queued
-    char* p;
-    hipStream_t s;
-    ~HFree() {
-      if (p) {
-        (void)hipStreamSynchronize(s);
-        (void)hipHostFree(p);
-      }
-    }
-  } hguard{hbuf, hs};
+  } drain{hs};
   double* h_theta = (double*)hbuf;
   double* h_pnorm = h_theta + (size_t)B * N;
   int32_t* h_sched = (int32_t*)(h_pnorm + (size_t)B * S);
@@ -548,7 +538,8 @@ static hg_status eval_impl(hg_problem* p, const hg_eval_desc* d, hg_result* resu
     // FP64 arithmetic bound (u = 2^-53) for both precisions: the schedule is
     // chosen by the paper's rule for double arithmetic; complex64 then differs
     // from complex128 only in the arithmetic of the products.
-    st = hg_plan(h_theta, (int64_t)B * N, p->sigma, d->tau, std::ldexp(1.0, -53), h_m, h_s);
+    st = plan_impl(h_theta, (int64_t)B * N, p->sigma, d->tau, std::ldexp(1.0, -53), h_m, h_s,
+                   table, d->rule);
     if (st != HG_OK) return st;
   }
   HG_HIP(hipMemcpyAsync(d_sched, h_sched, (size_t)2 * B * N * 4, hipMemcpyHostToDevice, hs));
@@ -607,6 +598,7 @@ static hg_status eval_impl(hg_problem* p, const hg_eval_desc* d, hg_result* resu
   HG_HIP(hipMemcpyAsync(h_res, bf.res, (size_t)B * 8 * 8, hipMemcpyDeviceToHost, hs));
   HG_HIP(hipMemcpyAsync(h_drift, bf.drift, (size_t)B * S * 8, hipMemcpyDeviceToHost, hs));
   HG_HIP(hipStreamSynchronize(hs));
+  drain.armed = false;
   float ms_f = 0.f, ms_b = 0.f;
   if (d->flags & HG_FLAG_TIMING) {
     HG_HIP(hipEventElapsedTime(&ms_f, bf.ev[0], bf.ev[1]));
@@ -642,6 +634,98 @@ static hg_status eval_impl(hg_problem* p, const hg_eval_desc* d, hg_result* resu
 }
 
 
+// Checks, launch shape and buffer sizes of one evaluation (shared by the
+// entry points that bring their own memory).
+static hg_status eval_prepare(hg_problem* p, const hg_eval_desc* d, hg_result* results,
+                              SweepShape* sh, Workspace* w) {
+  hg_status st = check_desc(p, d);
+  if (st != HG_OK) return st;
+  if (!results) return fail(HG_ERR_INVALID_ARG, "results is NULL");
+  const int B = d->n_batch, N = d->n_steps, S = d->n_states, K = p->n_ctrl;
+  const bool c128 = d->dtype == HG_C128;
+  HG_HIP(hipSetDevice(p->ctx->device));
+  std::string why;
+  *sh = SweepShape{};
+  if (!p->dense &&
+      !sweep_supported(p->ops, (int)p->dim, K, c128, p->ctx->lds_per_block, sh, &why))
+    return fail(HG_ERR_UNSUPPORTED, why);
+  sh->n_steps = N;
+  sh->n_states = S;
+  sh->n_batch = B;
+  const int ck = d->mode == HG_MODE_CHECKPOINT ? std::min(d->ckpt_every, N) : 0;
+  *w = layout(p, B, N, S, c128, ck, d->w_int != 0.0);
+  return HG_OK;
+}
+
+}  // extern "C"
+
+namespace hg {
+hg_status eval_on_buffers(hg_problem* p, const hg_eval_desc* d, hg_result* results, double* grad,
+                          hipStream_t hs, void* ws, size_t ws_bytes, void* hbuf,
+                          size_t hbuf_bytes, bool build_table) {
+  SweepShape sh;
+  Workspace w;
+  hg_status st = eval_prepare(p, d, results, &sh, &w);
+  if (st != HG_OK) return st;
+  if (w.total > ws_bytes)
+    return fail(HG_ERR_OUT_OF_MEMORY, "the evaluation needs " + std::to_string(w.total) +
+                                          " bytes of device workspace; " +
+                                          std::to_string(ws_bytes) + " are available");
+  const size_t hb = host_stage_bytes(d->n_batch, d->n_steps, d->n_states);
+  if (hb > hbuf_bytes)
+    return fail(HG_ERR_OUT_OF_MEMORY, "the evaluation needs " + std::to_string(hb) +
+                                          " bytes of host staging; " + std::to_string(hbuf_bytes) +
+                                          " are available");
+  return eval_core(p, d, results, grad, hs, sh, w, (char*)ws, (char*)hbuf, build_table);
+}
+}  // namespace hg
+
+extern "C" {
+
+// Host staging of the calling thread: pinned, grown on demand and kept for the
+// thread's lifetime, so a steady stream of evaluations pins no new memory.
+namespace {
+struct HostStage {
+  char* p = nullptr;
+  size_t n = 0;
+  ~HostStage() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+thread_local HostStage t_stage;
+}  // namespace
+
+static hg_status eval_impl(hg_problem* p, const hg_eval_desc* d, hg_result* results, double* grad,
+                           void* stream) {
+  SweepShape sh;
+  Workspace w;
+  hg_status st = eval_prepare(p, d, results, &sh, &w);
+  if (st != HG_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  // stream-ordered workspace from the device's default pool, whose release
+  // threshold hg_create raises so that freed blocks stay in the pool
+  char* ws = nullptr;
+  if (hipMallocAsync((void**)&ws, w.total, hs) != hipSuccess)
+    return fail(HG_ERR_OUT_OF_MEMORY, "workspace of " + std::to_string(w.total) + " bytes");
+  struct Free {
+    char* p;
+    hipStream_t s;
+    ~Free() {
+      if (p) (void)hipFreeAsync(p, s);
+    }
+  } guard{ws, hs};
+  const size_t hbytes = host_stage_bytes(d->n_batch, d->n_steps, d->n_states);
+  if (t_stage.n < hbytes) {
+    if (t_stage.p) HG_HIP(hipHostFree(t_stage.p));
+    t_stage.p = nullptr;
+    t_stage.n = 0;
+    const size_t want = std::max(hbytes, (size_t)1 << 20);
+    HG_HIP(hipHostMalloc((void**)&t_stage.p, want, hipHostMallocDefault));
+    t_stage.n = want;
+  }
+  return eval_core(p, d, results, grad, hs, sh, w, ws, t_stage.p, true);
+}
+
 hg_status hg_problem_create(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, const hg_csr* H0,
                             const hg_csr* Hk, const double* omega_diag, hg_problem** out) {
   return guarded("hg_problem_create", [&] {
@@ -661,9 +745,31 @@ hg_status hg_plan(const double* theta, int64_t n, int32_t sigma, double tau, dou
   return guarded("hg_plan", [&] { return plan_impl(theta, n, sigma, tau, u, m_out, s_out); });
 }
 
+hg_status hg_plan_rule(const double* theta, int64_t n, int32_t sigma, double tau, double u,
+                       int32_t rule, int32_t* m_out, int32_t* s_out) {
+  return guarded("hg_plan_rule", [&] {
+    return plan_impl(theta, n, sigma, tau, u, m_out, s_out, true, rule);
+  });
+}
+
 hg_status hg_eval(hg_problem* p, const hg_eval_desc* d, hg_result* results, double* grad,
                   void* stream) {
   return guarded("hg_eval", [&] { return eval_impl(p, d, results, grad, stream); });
+}
+
+hg_status hg_mem_pool_peak(hg_ctx* ctx, int32_t reset, size_t* used_high) {
+  if (!ctx || !used_high) return fail(HG_ERR_INVALID_ARG, "NULL argument");
+  HG_HIP(hipSetDevice(ctx->device));
+  hipMemPool_t pool;
+  HG_HIP(hipDeviceGetDefaultMemPool(&pool, ctx->device));
+  uint64_t v = 0;
+  HG_HIP(hipMemPoolGetAttribute(pool, hipMemPoolAttrUsedMemHigh, &v));
+  *used_high = (size_t)v;
+  if (reset) {
+    uint64_t z = 0;
+    HG_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrUsedMemHigh, &z));
+  }
+  return HG_OK;
 }
 
 }  // extern "C"

@@ -75,9 +75,22 @@ namespace hg {
 // bound of App. C.
 double error_bound(double theta, int m, int s, int sigma, double u);
 // Returns 0 on success, 1 if unreachable, 2 if a solution would need s > 4096
-// (then *fail_index is the failing index).
+// (then *fail_index is the failing index).  With build_table, the threshold
+// table of (sigma, tau, u) is built and cached on first use (host memory);
+// without, a cached table is used as far as it reaches and the direct search
+// decides the rest (the same decisions, no allocation).  rule: HG_PLAN_SMALLEST_S
+// (the paper's) or HG_PLAN_MIN_MU (fewest products under the same bound).
 int plan_steps(const double* theta, int64_t n, int sigma, double tau, double u,
-               int32_t* m_out, int32_t* s_out, int64_t* fail_index);
+               int32_t* m_out, int32_t* s_out, int64_t* fail_index, bool build_table = true,
+               int rule = 0);
+
+// One evaluation (hg_eval's work) on caller-provided memory: `ws` device
+// workspace of ws_bytes, `hbuf` host staging of hbuf_bytes (pinned or not).
+// OUT_OF_MEMORY when either is too small for the shape.  See plan_steps for
+// build_table.
+hg_status eval_on_buffers(hg_problem* p, const hg_eval_desc* d, hg_result* results, double* grad,
+                          hipStream_t hs, void* ws, size_t ws_bytes, void* hbuf,
+                          size_t hbuf_bytes, bool build_table);
 
 // Kernel launchers (kernels.hip).
 struct SweepShape {

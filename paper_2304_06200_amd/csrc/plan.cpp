@@ -107,6 +107,37 @@ static int select_one(double theta, int sigma, double tau, double u, int32_t* m_
   return capped ? 2 : 1;
 }
 
+// Fewest products mu = m s under the same bound (ties: the smaller s).  For
+// each s the smallest feasible m is the cheapest; s beyond the best mu found
+// cannot win.  Same return codes as select_one.
+static int select_one_min_mu(double theta, int sigma, double tau, double u, int32_t* m_out,
+                             int32_t* s_out) {
+  const double up = u_prime(u);
+  const double g3 = gamma_n(3, up);
+  int64_t s_lim = (int64_t)(tau / g3);
+  if (s_lim < 1) s_lim = 1;
+  const bool capped = s_lim > kSCap;
+  if (capped) s_lim = kSCap;
+  int64_t best = -1;
+  for (int64_t s = 1; s <= s_lim; ++s) {
+    if (best >= 0 && s > best) break;
+    const double x = theta / (double)s;
+    for (int m = 1; m <= 60; ++m) {
+      if (error_bound(theta, m, (int)s, sigma, u) <= tau) {
+        if (best < 0 || (int64_t)m * s < best) {
+          best = (int64_t)m * s;
+          *m_out = m;
+          *s_out = (int32_t)s;
+        }
+        break;
+      }
+      if ((double)s * beta_of(x, m, sigma, up) > 2.0 * tau) break;
+    }
+  }
+  if (best >= 0) return 0;
+  return capped ? 2 : 1;
+}
+
 namespace {
 
 // Feasibility thresholds for fixed (sigma, tau, u): th[s][m] is the largest
@@ -192,22 +223,86 @@ bool near(double a, double b) { return b >= 0.0 && std::fabs(a - b) <= 1e-12 * s
 }  // namespace
 
 int plan_steps(const double* theta, int64_t n, int sigma, double tau, double u, int32_t* m_out,
-               int32_t* s_out, int64_t* fail_index) {
-  std::shared_ptr<Thresholds> tab = table_for(sigma, tau, u);
+               int32_t* s_out, int64_t* fail_index, bool build_table, int rule) {
+  std::shared_ptr<Thresholds> tab;
+  if (build_table) {
+    tab = table_for(sigma, tau, u);
+  } else {
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto it = g_tabs.find(std::make_tuple(sigma, tau, u));
+    if (it != g_tabs.end()) tab = it->second;
+  }
+  auto direct = rule == 1 ? select_one_min_mu : select_one;
+  if (!tab) {  // direct search only
+    for (int64_t i = 0; i < n; ++i) {
+      const int rc = direct(theta[i], sigma, tau, u, &m_out[i], &s_out[i]);
+      if (rc != 0) {
+        *fail_index = i;
+        return rc;
+      }
+    }
+    return 0;
+  }
   std::lock_guard<std::mutex> lk(g_tab_mu);  // the table grows lazily
+  if (rule == 1) {
+    for (int64_t i = 0; i < n; ++i) {
+      const double t = theta[i];
+      int64_t best = -1;
+      int bm = 0;
+      int64_t bs = 0;
+      bool exact = true;
+      for (int64_t s = 1; s <= tab->s_lim; ++s) {
+        if (best >= 0 && s > best) break;
+        if (!build_table && (int64_t)tab->th.size() <= s) {
+          exact = false;
+          break;
+        }
+        tab->extend(s);
+        for (int m = 1; m <= 60; ++m)
+          if (near(t, tab->th[s][m])) exact = false;
+        if (!exact) break;
+        if (t <= tab->smax[s]) {
+          int m = 1;
+          while (m <= 60 && !(t <= tab->th[s][m])) ++m;
+          if (m <= 60 && (best < 0 || (int64_t)m * s < best)) {
+            best = (int64_t)m * s;
+            bm = m;
+            bs = s;
+          }
+        }
+      }
+      if (exact && best >= 0) {
+        m_out[i] = bm;
+        s_out[i] = (int32_t)bs;
+        continue;
+      }
+      const int rc = select_one_min_mu(t, sigma, tau, u, &m_out[i], &s_out[i]);
+      if (rc != 0) {
+        *fail_index = i;
+        return rc;
+      }
+    }
+    return 0;
+  }
   for (int64_t i = 0; i < n; ++i) {
     const double t = theta[i];
     // smallest s whose best threshold admits t, growing the table as needed
+    // (without build_table, only as far as it already reaches)
     int64_t s = 1;
     bool found = false;
+    bool beyond = false;
     for (; s <= tab->s_lim; ++s) {
+      if (!build_table && (int64_t)tab->th.size() <= s) {
+        beyond = true;
+        break;
+      }
       tab->extend(s);
       if (t <= tab->smax[s]) {
         found = true;
         break;
       }
     }
-    bool exact = found;
+    bool exact = found && !beyond;
     int m = 0;
     if (found) {
       for (m = 1; m <= 60; ++m)

@@ -35,6 +35,7 @@ struct Request {
   std::vector<int32_t> schedule;  // private copy of a frozen schedule
   hg_result* results = nullptr;
   double* grad = nullptr;
+  hipEvent_t ready = nullptr;     // recorded on the caller's stream at submit
   size_t bytes = 0;
   int state = 0;  // 0 queued, 1 running, 2 done
   hg_status status = HG_OK;
@@ -82,11 +83,23 @@ void worker_loop(hg_server* sv, int w) {
       r->t_start = Clock::now();
     }
     if (!r->schedule.empty()) r->desc.schedule = r->schedule.data();
-    hg_status st;
+    hg_status st = HG_OK;
     std::string err;
     try {  // no exception may end a worker thread (or cross the C ABI)
-      st = hg_eval(r->p, &r->desc, r->results, r->grad, sv->streams[w]);
-      if (st != HG_OK) err = hg_last_error();
+      // the inputs are complete once the caller's stream reaches the submit point
+      if (r->ready) {
+        const hipError_t e = hipStreamWaitEvent(sv->streams[w], r->ready, 0);
+        (void)hipEventDestroy(r->ready);
+        r->ready = nullptr;
+        if (e != hipSuccess) {
+          st = HG_ERR_DEVICE;
+          err = std::string("hipStreamWaitEvent: ") + hipGetErrorString(e);
+        }
+      }
+      if (st == HG_OK) {
+        st = hg_eval(r->p, &r->desc, r->results, r->grad, sv->streams[w]);
+        if (st != HG_OK) err = hg_last_error();
+      }
     } catch (const std::bad_alloc&) {
       st = HG_ERR_OUT_OF_MEMORY;
       err = "host allocation failed";
@@ -164,7 +177,8 @@ hg_status hg_server_create(hg_ctx* ctx, size_t hbm_budget_bytes, int32_t max_inf
 }
 
 hg_status hg_server_submit(hg_server* sv, hg_problem* p, const hg_eval_desc* desc,
-                           hg_result* results, double* grad, uint64_t* req_id) {
+                           hg_result* results, double* grad, void* after_stream,
+                           uint64_t* req_id) {
   if (!sv || !p || !desc || !results || !req_id) {
     hg::set_error("hg_server_submit: NULL argument");
     return HG_ERR_INVALID_ARG;
@@ -188,6 +202,33 @@ hg_status hg_server_submit(hg_server* sv, hg_problem* p, const hg_eval_desc* des
                   std::to_string(sv->budget) + " B");
     return HG_ERR_OUT_OF_MEMORY;
   }
+  // the request's worker waits for what the caller queued on after_stream so far
+  int prev_dev = -1;
+  (void)hipGetDevice(&prev_dev);
+  const bool made = hipSetDevice(sv->ctx->device) == hipSuccess &&
+                    hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) == hipSuccess;
+  if (prev_dev >= 0 && prev_dev != sv->ctx->device) (void)hipSetDevice(prev_dev);
+  if (!made) {
+    r->ready = nullptr;
+    hg::set_error("hg_server_submit: hipEventCreate failed");
+    return HG_ERR_DEVICE;
+  }
+  if (hipEventRecord(r->ready, (hipStream_t)after_stream) != hipSuccess) {
+    (void)hipEventDestroy(r->ready);
+    r->ready = nullptr;
+    hg::set_error("hg_server_submit: hipEventRecord on the caller's stream failed");
+    return HG_ERR_DEVICE;
+  }
+  struct Unready {  // a request refused below never reaches a worker
+    Request* r;
+    bool armed = true;
+    ~Unready() {
+      if (armed && r->ready) {
+        (void)hipEventDestroy(r->ready);
+        r->ready = nullptr;
+      }
+    }
+  } unready{r.get()};
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stopping) {
@@ -203,6 +244,7 @@ hg_status hg_server_submit(hg_server* sv, hg_problem* p, const hg_eval_desc* des
     sv->queue.push_back(r);
     sv->reqs[r->id] = r;
     *req_id = r->id;
+    unready.armed = false;
   }
   sv->cv_work.notify_one();
   return HG_OK;
@@ -264,6 +306,10 @@ hg_status hg_server_cancel(hg_server* sv, uint64_t req_id) {
         sv->queue.erase(q);
         break;
       }
+    if (r->ready) {
+      (void)hipEventDestroy(r->ready);
+      r->ready = nullptr;
+    }
     r->state = 2;
     r->status = HG_ERR_CANCELLED;
     r->error = "cancelled before it ran";

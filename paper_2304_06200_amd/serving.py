@@ -32,7 +32,12 @@ class Server:
                renorm_every: Optional[int] = None, mode: str = "reconstruct",
                ckpt_every: int = 0) -> Handle:
         """u: float64 device tensor (K, N) or (B, K, N); psi0, targets: complex128
-        device tensors (S, d) or (B, S, d).  Returns a handle for wait()."""
+        device tensors (S, d) or (B, S, d).  Returns a handle for wait().
+
+        The inputs may still be being produced on torch's current stream: the
+        request's device work waits for everything queued there up to this
+        call (including the copies made here), so no synchronisation is needed
+        before submit.  The gradient tensor is complete once wait() returns."""
         import torch
         if u.dim() == 2:
             u = u.unsqueeze(0)
@@ -55,7 +60,8 @@ class Server:
         grad = torch.empty((B, K, N), dtype=torch.float64, device=u.device) if K > 0 else None
         res = (L.hg_result * B)()
         rid = L.hg_server_submit(self.handle, problem.handle, desc, res,
-                                 int(grad.data_ptr()) if grad is not None else None)
+                                 int(grad.data_ptr()) if grad is not None else None,
+                                 torch.cuda.current_stream(u.device).cuda_stream)
         return Handle(rid, B, (u, psi0, targets, problem), res, grad)
 
     def poll(self, h: Handle) -> bool:

@@ -1,0 +1,46 @@
+"""The min-mu planner rule on the GPU path: the library's planner picks the
+oracle's min-mu schedule from its own norms, and the evaluation matches the
+Taylor-discretised oracle on that schedule."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from gpu_common import assert_parity, log, make_problem, run
+from workloads.configs import serving_request
+
+pytestmark = pytest.mark.gpu
+
+
+def _schedule(p, rule, tau):
+    from oracle import planner
+    import scipy.sparse as sp
+    pat = abs(p.H0)
+    for h in p.Hk:
+        pat = pat + abs(h)
+    sigma = int(np.max(np.diff(sp.csr_matrix(pat).indptr)))
+    pick = planner.select_min_mu if rule == "min_mu" else planner.select
+    out = np.zeros((2, p.n_steps), dtype=np.int32)
+    for n in range(p.n_steps):
+        H = p.H0 + sum(p.u[k, n] * p.Hk[k] for k in range(p.n_ctrl))
+        theta = float(np.max(np.asarray(abs(-1j * p.dt * H).sum(axis=0))))
+        out[:, n] = pick(theta, sigma, tau)
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_min_mu_rule(dtype):
+    """transmon(3) x cavity(700), d = 2100, dt = 1 ns (norms 24-40), tau = 1e-12:
+    8 of 24 steps take a different (m, s) under min-mu."""
+    from oracle import taylor
+    p = dataclasses.replace(serving_request(3, 700, 24, 2), tau=1e-12)
+    sched = _schedule(p, "min_mu", p.tau)
+    base = _schedule(p, "smallest_s", p.tau)
+    assert np.sum(sched[0] * sched[1]) < np.sum(base[0] * base[1])
+    ref = taylor.hg_discrete(p.H0, p.Hk, p.u, p.dt, p.psi0, p.targets, sched, omega=p.omega,
+                             w_fid=p.w_fid, w_pen=p.w_pen)
+    log(f"[case] min-mu rule d=2100 N=24 S=2 {dtype}: sum mu {int(np.sum(sched[0] * sched[1]))} "
+        f"vs {int(np.sum(base[0] * base[1]))}")
+    r = run(p, dtype, rule="min_mu")
+    assert int(r.sum_mu[0]) == int(np.sum(sched[0] * sched[1]))
+    assert_parity(r, ref, dtype, label="min-mu")

@@ -131,3 +131,46 @@ def test_dense_and_dia_problems_in_one_stream():
         alone = hg.evaluate(prob, *_dev(p), p.dt, **_kw(p, "c64"))
         assert r.cost[0] == alone.cost[0], p.name
         assert np.array_equal(r.grad.cpu().numpy(), alone.grad.cpu().numpy()), p.name
+
+
+def test_submit_waits_for_inputs_on_caller_stream():
+    """Requests whose inputs are still being produced on torch's current
+    stream when submit is called (a long GEMM chain first, then the amplitudes
+    and states written by a kernel that depends on it), batched (B = 3) and
+    with (S, d) states expanded by submit itself: every result equals the
+    synchronous evaluate() of the same inputs, bitwise."""
+    import torch
+    import paper_2304_06200_amd as hg
+    reqs = _stream(4, seed=11)
+    sv = hg.Server(context(), hbm_budget_bytes=4 << 30, max_inflight=4)
+    log("[case] serving: inputs produced on the caller's stream right before submit, B=3")
+    rng = np.random.default_rng(12)
+    side = torch.cuda.Stream()
+    handles, inputs = [], []
+    with torch.cuda.stream(side):
+        for p in reqs:
+            u_host = np.stack([p.u, p.u * 0.9, p.u * 1.1])
+            u_src = torch.tensor(u_host, dtype=torch.float64, device="cuda")
+            psi_src = torch.tensor(p.psi0, dtype=torch.complex128, device="cuda")
+            tg_src = torch.tensor(p.targets, dtype=torch.complex128, device="cuda")
+            torch.cuda.synchronize()
+            big = torch.tensor(rng.standard_normal((2048, 2048)), dtype=torch.float32,
+                               device="cuda")
+            for _ in range(12):
+                big = (big @ big) * (1.0 / 2048)
+            zero = (big.sum() * 0.0).to(torch.float64)  # finite, depends on the chain
+            u = torch.empty_like(u_src)
+            u.copy_(u_src + zero)
+            psi = torch.empty_like(psi_src)
+            psi.copy_(psi_src + zero)
+            h = sv.submit(_problem(p), u, psi, tg_src, p.dt, **_kw(p, "c64"))
+            handles.append(h)
+            inputs.append((u_src, psi_src, tg_src))
+    out = [sv.wait(h) for h in handles]
+    sv.close()
+    torch.cuda.synchronize()
+    for p, (u_src, psi_src, tg_src), (r, _, _) in zip(reqs, inputs, out):
+        alone = hg.evaluate(_problem(p), u_src, psi_src, tg_src, p.dt, **_kw(p, "c64"))
+        for b in range(3):
+            assert r.cost[b] == alone.cost[b], (p.name, b)
+        assert np.array_equal(r.grad.cpu().numpy(), alone.grad.cpu().numpy()), p.name

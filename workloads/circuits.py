@@ -155,3 +155,40 @@ class Problem:
     @property
     def n_states(self) -> int:
         return self.psi0.shape[0]
+
+
+def fock_transmon_cavity(d_t: int, d_c: int, delta: float, alpha: float, g: float):
+    """The paper's Fock-state benchmark system (Sec. IV.B, eq. fockH), in the
+    frame co-rotating with the transmon drive:
+
+    H0 = Delta b^dag b + (alpha/2) b^dag b (b^dag b - 1) + g (c b^dag + c^dag b)
+    Controls: b^dag b (longitudinal a_z) and b + b^dag (transverse a_x).
+    Product basis transmon x cavity (cavity index fastest).
+    """
+    dims = (d_t, d_c)
+    b = embed(destroy(d_t), 0, dims)
+    c = embed(destroy(d_c), 1, dims)
+    nt = embed(number(d_t), 0, dims)
+    ident = sp.identity(d_t * d_c, dtype=np.complex128, format="csr")
+    H0 = delta * nt + 0.5 * alpha * (nt @ (nt - ident)) + g * (c @ b.conj().T + c.conj().T @ b)
+    return _clean(H0), [_clean(nt), _clean(b + b.conj().T)], dims
+
+
+def qubit_chain(n_q: int, g: float):
+    """Driven qubit chain with nearest-neighbour sigma_z coupling (App. E, H_3):
+
+    H0 = g sum_{nu < n_q} sigma_z^(nu) sigma_z^(nu+1)
+    Controls: sigma_x^(nu), sigma_y^(nu) for every qubit (x then y, qubit by qubit).
+    """
+    sx = sp.csr_matrix(np.array([[0, 1], [1, 0]], dtype=np.complex128))
+    sy = sp.csr_matrix(np.array([[0, -1j], [1j, 0]], dtype=np.complex128))
+    sz = sp.csr_matrix(np.array([[1, 0], [0, -1]], dtype=np.complex128))
+    dims = (2,) * n_q
+    z = [embed(sz, i, dims) for i in range(n_q)]
+    H0 = sp.csr_matrix((2 ** n_q, 2 ** n_q), dtype=np.complex128)
+    for i in range(n_q - 1):
+        H0 = H0 + g * (z[i] @ z[i + 1])
+    ctrls = []
+    for i in range(n_q):
+        ctrls.extend([embed(sx, i, dims), embed(sy, i, dims)])
+    return _clean(H0), ctrls, dims
