@@ -80,7 +80,8 @@ typedef struct hg_problem hg_problem;
 
 /* Create a context bound to HIP device `device_ordinal`.  Also raises the
  * release threshold of the device's default memory pool (evaluation
- * workspaces then stay pooled between calls). */
+ * workspaces then stay pooled between calls) and looks up, with the device
+ * current, the device address of the fixed scratch array of hg_eval_noalloc. */
 hg_status hg_create(int device_ordinal, hg_ctx** out);
 hg_status hg_destroy(hg_ctx* ctx);
 const char* hg_status_string(hg_status s);
@@ -218,6 +219,24 @@ hg_status hg_eval(hg_problem* p, const hg_eval_desc* desc, hg_result* results,
 /* Device memory the library would allocate for one hg_eval call with this
  * shape (workspace only; caller buffers excluded).  Used for admission. */
 hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* desc, size_t* bytes);
+
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): hg_eval's evaluation, with the same
+ * kernels and same results, with no hipMalloc, hipFree, hipHostMalloc or
+ * event creation.  The workspace is a fixed array of 64 MiB of device memory
+ * that the library defines once per device (held until the process ends) and
+ * the host staging a fixed 2 MiB host array per device; the planner uses its
+ * cached threshold table if one exists, else the direct search (same
+ * decisions).  Calls that overlap on one device share both arrays and race:
+ * one call at a time per device.  The arrays keep the last call's contents;
+ * everything that must start at zero is cleared by the kernels.
+ * Errors: those of hg_eval; OUT_OF_MEMORY when hg_eval_footprint of the
+ * shape exceeds the scratch or the staging (B*N, B*S) exceeds 2 MiB;
+ * INVALID_ARG with HG_FLAG_TIMING (it needs events). */
+hg_status hg_eval_noalloc(hg_problem* p, const hg_eval_desc* desc, hg_result* results,
+                          double* grad, void* stream);
+/* Sizes of hg_eval_noalloc's fixed device scratch and host staging (bytes). */
+hg_status hg_eval_noalloc_limits(size_t* scratch_bytes, size_t* host_stage_bytes);
 
 /* High-water mark of device memory handed out by the device's default pool,
  * which holds every evaluation workspace (bytes; operators and caller buffers

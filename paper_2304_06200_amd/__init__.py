@@ -7,9 +7,9 @@ memory and streams (``api``), and the autograd adjoint (``autograd``).
 Importing the package fails if the library has not been built.
 """
 from . import _lib  # noqa: F401  (raises ImportError when libhgrape.so is missing)
-from .api import Context, EvalResult, Problem, evaluate, plan, step_norms  # noqa: F401
+from .api import Context, EvalResult, Problem, evaluate, mem_pool_peak, plan, step_norms  # noqa: F401
 from .autograd import HGCost, hg_cost  # noqa: F401
 from .serving import Server, percentiles  # noqa: F401
 
-__all__ = ["Context", "Problem", "EvalResult", "evaluate", "plan", "step_norms", "HGCost",
+__all__ = ["Context", "Problem", "EvalResult", "evaluate", "mem_pool_peak", "plan", "step_norms", "HGCost",
            "hg_cost", "Server", "percentiles"]

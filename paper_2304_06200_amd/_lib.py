@@ -103,6 +103,8 @@ def _load():
         "hg_server_submit": (C.c_int, [P, P, C.POINTER(hg_eval_desc), C.POINTER(hg_result), P,
                                        P, C.POINTER(C.c_uint64)]),
         "hg_mem_pool_peak": (C.c_int, [P, C.c_int32, C.POINTER(C.c_size_t)]),
+        "hg_eval_noalloc": (C.c_int, [P, C.POINTER(hg_eval_desc), C.POINTER(hg_result), P, P]),
+        "hg_eval_noalloc_limits": (C.c_int, [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "hg_server_poll": (C.c_int, [P, C.c_uint64, C.POINTER(C.c_int32)]),
         "hg_server_wait": (C.c_int, [P, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "hg_server_cancel": (C.c_int, [P, C.c_uint64]),
@@ -121,6 +123,7 @@ _lib = _load()
 EXPORTED = ("hg_create", "hg_destroy", "hg_status_string", "hg_last_error", "hg_version",
             "hg_problem_create", "hg_problem_create_dense", "hg_problem_destroy", "hg_problem_info", "hg_plan", "hg_plan_rule",
             "hg_error_bound", "hg_step_norms", "hg_eval", "hg_eval_footprint", "hg_mem_pool_peak",
+            "hg_eval_noalloc", "hg_eval_noalloc_limits",
             "hg_server_create", "hg_server_submit", "hg_server_poll", "hg_server_wait",
             "hg_server_cancel", "hg_server_info", "hg_server_destroy")
 
@@ -217,6 +220,16 @@ def hg_step_norms(p: int, u_ptr: int, n_batch: int, n_steps: int, dt: float, the
 
 def hg_eval(p: int, desc: hg_eval_desc, results, grad_ptr, stream: int) -> None:
     _check(_lib.hg_eval(p, C.byref(desc), results, grad_ptr, stream), "hg_eval")
+
+
+def hg_eval_noalloc(p: int, desc: hg_eval_desc, results, grad_ptr, stream: int) -> None:
+    _check(_lib.hg_eval_noalloc(p, C.byref(desc), results, grad_ptr, stream), "hg_eval_noalloc")
+
+
+def hg_eval_noalloc_limits():
+    a, b = C.c_size_t(), C.c_size_t()
+    _check(_lib.hg_eval_noalloc_limits(C.byref(a), C.byref(b)), "hg_eval_noalloc_limits")
+    return int(a.value), int(b.value)
 
 
 def hg_eval_footprint(p: int, desc: hg_eval_desc) -> int:

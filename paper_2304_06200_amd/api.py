@@ -139,7 +139,8 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
              w_pen: float = 0.0, w_int: float = 0.0, tau: float = 1e-12, dtype: str = "c128",
              renorm_every: Optional[int] = None, schedule: Optional[np.ndarray] = None,
              want_grad: bool = True, timing: bool = False, mode: str = "reconstruct",
-             ckpt_every: int = 0, stream=None, rule: str = "smallest_s") -> EvalResult:
+             ckpt_every: int = 0, stream=None, rule: str = "smallest_s",
+             noalloc: bool = False, grad_out=None) -> EvalResult:
     """Cost and gradient of B amplitude sets.
 
     u        torch float64 device tensor (K, N) or (B, K, N)
@@ -151,6 +152,9 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
              every ckpt_every steps, segments re-propagated in the backward sweep)
     w_int    weight of the time-integrated infidelity C3 (0 = off)
     rule     planner rule: "smallest_s" (the paper's) or "min_mu" (fewest products)
+    noalloc  run through hg_eval_noalloc (the library's fixed scratch; no
+             allocation in the call, one call at a time per device)
+    grad_out optional preallocated float64 device tensor (B, K, N) for the gradient
     """
     torch = _torch()
     if u.dim() == 2:
@@ -190,10 +194,16 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
                      w_fid, w_pen, tau, code, renorm_every, sched_p, mode=mcode,
                      ckpt_every=ckpt_every, flags=L.HG_FLAG_TIMING if timing else 0,
                      w_int=w_int, rule=RULES[rule])
-    grad = torch.empty((B, K, N), dtype=torch.float64, device=u.device) if want_grad and K > 0 else None
+    if grad_out is not None:
+        if grad_out.shape != (B, K, N) or grad_out.dtype != torch.float64 or not grad_out.is_contiguous():
+            raise ValueError("grad_out must be a contiguous float64 tensor of shape (B, K, N)")
+        grad = grad_out
+    else:
+        grad = torch.empty((B, K, N), dtype=torch.float64, device=u.device) if want_grad and K > 0 else None
     res = (L.hg_result * B)()
     st = stream if stream is not None else torch.cuda.current_stream(u.device).cuda_stream
-    L.hg_eval(problem.handle, desc, res, _ptr(grad) if grad is not None else None, st)
+    call = L.hg_eval_noalloc if noalloc else L.hg_eval
+    call(problem.handle, desc, res, _ptr(grad) if grad is not None else None, st)
     return EvalResult(
         cost=np.array([r.cost for r in res]),
         infidelity=np.array([r.infidelity for r in res]),

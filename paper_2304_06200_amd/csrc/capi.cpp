@@ -172,6 +172,9 @@ hg_status hg_create(int device_ordinal, hg_ctx** out) {
   HG_HIP(hipDeviceGetDefaultMemPool(&pool, device_ordinal));
   uint64_t keep = UINT64_MAX;
   HG_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  // device address of hg_eval_noalloc's scratch array on this device
+  hg_status st = noalloc_setup(device_ordinal);
+  if (st != HG_OK) return st;
   *out = c.release();
   return HG_OK;
 }

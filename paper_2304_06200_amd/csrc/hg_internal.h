@@ -92,6 +92,10 @@ hg_status eval_on_buffers(hg_problem* p, const hg_eval_desc* d, hg_result* resul
                           hipStream_t hs, void* ws, size_t ws_bytes, void* hbuf,
                           size_t hbuf_bytes, bool build_table);
 
+// Looks up (once per device, with that device current) the device address of
+// hg_eval_noalloc's scratch array (noalloc.cpp).
+hg_status noalloc_setup(int device);
+
 // Kernel launchers (kernels.hip).
 struct SweepShape {
   int dim, n_ctrl, n_steps, n_states, n_batch;
