@@ -96,9 +96,18 @@ int32_t hg_version(void);
  * diagonal, zero outside the matrix), each operator's values on it; each Hk
  * also gets its own diagonals for the derivative products.  Duplicate CSR
  * entries are summed, explicit zeros dropped.
+ * A state column is swept by one workgroup holding its term vectors in LDS
+ * (Sec. III.C's forward-backward sweep per state).  When a column does not
+ * fit one workgroup in some precision (complex128 beyond about 2048 rows,
+ * either precision beyond 4096), the problem also gets a split layout: the
+ * rows, seen as blocks of L (row = t L + c, every union offset either a
+ * multiple of L or short and inside its block -- e.g. the cavity index of a
+ * transmon x cavity basis), are divided by c-range over P co-resident
+ * workgroups that exchange their edge rows after every Taylor term.
  * Errors: INVALID_ARG (bad CSR, dim < 1, n_ctrl < 0), NOT_HERMITIAN,
  * NONFINITE, UNSUPPORTED (more than 13 union diagonals, more than 4 diagonals
- * in one control, dim > 4096, n_ctrl > 16), DEVICE. */
+ * in one control, n_ctrl > 16, dim > 65536, or a column too long for one
+ * workgroup in both precisions with no split layout), DEVICE. */
 hg_status hg_problem_create(hg_ctx* ctx, int64_t dim, int32_t n_ctrl,
                             const hg_csr* H0, const hg_csr* Hk,
                             const double* omega_diag, hg_problem** out);
@@ -209,8 +218,11 @@ typedef struct {
  * stream-ordered from the device's default memory pool (freed blocks stay in
  * the pool, see hg_create) and the host staging is pinned memory kept per
  * calling thread, so repeated calls allocate nothing new.  One workgroup holds
- * one state column's term vectors in LDS: UNSUPPORTED when they do not fit
- * (e.g. complex128 above 2048 rows).
+ * one state column's term vectors in LDS, or P workgroups of the problem's
+ * split layout (see hg_problem_create; launched cooperatively, so
+ * n_batch * n_states * P must not exceed the compute units, else
+ * UNSUPPORTED; their bounded waits for each other end in DEVICE if a
+ * neighbour does not arrive within 20 s).
  * Errors: INVALID_ARG, NONFINITE, TOLERANCE_UNREACHABLE, UNSUPPORTED,
  * OUT_OF_MEMORY, DEVICE. */
 hg_status hg_eval(hg_problem* p, const hg_eval_desc* desc, hg_result* results,

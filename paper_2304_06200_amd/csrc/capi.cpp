@@ -121,6 +121,94 @@ hg_status guarded(const char* what, F&& f) {
   }
 }
 
+
+namespace hg {
+namespace {
+
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// Chooses the column split of a banded problem (see Split): the smallest halo
+// width h for which the offsets larger than h have a common block length L
+// with dim % L == 0 and no entry at an offset of at most h crosses a block,
+// then the fewest parts P whose local problem the kernels take in both
+// precisions.  Fills sp (without device arrays) or returns false with why.
+bool plan_split(const std::vector<std::vector<std::vector<Entry>>>& ops, int64_t dim,
+                const DevOps& g, int K, size_t lds, int num_cu, Split* sp, std::string* why) {
+  std::set<int64_t> mags;
+  mags.insert(0);
+  for (int e = 0; e < g.W; ++e)
+    if (g.off[e] != 0) mags.insert(std::llabs((int64_t)g.off[e]));
+  for (int64_t hh : mags) {
+    int64_t Lg = 0;
+    for (int e = 0; e < g.W; ++e)
+      if (std::llabs((int64_t)g.off[e]) > hh) Lg = gcd64(Lg, std::llabs((int64_t)g.off[e]));
+    const int64_t L = Lg ? Lg : dim;
+    if (L < 2 || dim % L != 0 || L <= 2 * hh) continue;
+    bool inside = true;
+    for (size_t o = 0; o < ops.size() && inside; ++o)
+      for (int64_t i = 0; i < dim && inside; ++i)
+        for (auto& en : ops[o][i])
+          if (en.col != i && std::llabs(en.col - i) <= hh && en.col / L != i / L) {
+            inside = false;
+            break;
+          }
+    if (!inside) continue;
+    const int64_t T = dim / L;
+    for (int P = 2; P <= kMaxParts; ++P) {
+      if (L / P < std::max<int64_t>(hh, 1)) break;
+      Split c;
+      c.P = P;
+      c.L = (int)L;
+      c.T = (int)T;
+      c.h = (int)hh;
+      int wmax = 0, c0 = 0;
+      for (int q = 0; q < P; ++q) {
+        c.w[q] = (int)(L / P + (q < L % P ? 1 : 0));
+        c.c0[q] = c0;
+        c0 += c.w[q];
+        wmax = std::max(wmax, c.w[q]);
+      }
+      c.seg = wmax + 2 * (int)hh;
+      if ((int64_t)T * c.seg > (int64_t)kMaxThreads * kMaxRows) continue;
+      c.d_loc = (int)T * c.seg;
+      auto local = [&](int o) {
+        return std::llabs((int64_t)o) <= hh ? o : (int)((int64_t)o / L) * c.seg;
+      };
+      c.ops.W = g.W;
+      c.ops.halo = 0;
+      for (int e = 0; e < g.W; ++e) {
+        c.ops.off[e] = local(g.off[e]);
+        c.ops.halo = std::max(c.ops.halo, std::abs(c.ops.off[e]));
+      }
+      for (int k = 0; k < K; ++k) {
+        c.ops.WK[k] = g.WK[k];
+        for (int q = 0; q < g.WK[k]; ++q) c.ops.offk[k][q] = local(g.offk[k][q]);
+      }
+      SweepShape sh{};
+      std::string w1, w2;
+      if (split_supported(c, K, true, lds, num_cu, &sh, &w1) &&
+          split_supported(c, K, false, lds, num_cu, &sh, &w2)) {
+        *sp = c;
+        return true;
+      }
+    }
+  }
+  *why = "no split of the rows over up to " + std::to_string(kMaxParts) +
+         " workgroups fits: the union offsets do not separate into a block length L (dim % L "
+         "== 0) and short offsets that stay inside their block";
+  return false;
+}
+
+}  // namespace
+}  // namespace hg
+
 hg_problem::~hg_problem() {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
@@ -128,6 +216,9 @@ hg_problem::~hg_problem() {
   if (ops.valk) (void)hipFree(ops.valk);
   if (ops.omega) (void)hipFree(ops.omega);
   if (dops.H) (void)hipFree(dops.H);
+  if (split.ops.vals) (void)hipFree(split.ops.vals);
+  if (split.ops.valk) (void)hipFree(split.ops.valk);
+  if (split.ops.omega) (void)hipFree(split.ops.omega);
 }
 
 extern "C" {
@@ -188,7 +279,7 @@ static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, c
                             const hg_csr* Hk, const double* omega_diag, bool dense,
                             hg_problem** out) {
   if (!ctx || !out || !H0) return fail(HG_ERR_INVALID_ARG, "NULL argument");
-  const int64_t dmax = dense ? (int64_t)kDenseMaxDim : (int64_t)kMaxThreads * kMaxRows;
+  const int64_t dmax = dense ? (int64_t)kDenseMaxDim : (int64_t)kMaxDimSplit;
   if (dim < 1 || dim > dmax)
     return fail(dim < 1 ? HG_ERR_INVALID_ARG : HG_ERR_UNSUPPORTED,
                 "dim must be in [1, " + std::to_string(dmax) + "]");
@@ -309,6 +400,55 @@ static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, c
     HG_HIP(hipMalloc(&d.omega, dim * sizeof(double)));
     HG_HIP(hipMemcpy(d.omega, omega_diag, dim * sizeof(double), hipMemcpyHostToDevice));
   }
+  // Rows beyond one workgroup (in either precision): split the columns.
+  {
+    SweepShape sh{};
+    std::string w64, w128;
+    const bool one64 = dim <= (int64_t)kMaxThreads * kMaxRows &&
+                       sweep_supported(d, (int)dim, K, false, ctx->lds_per_block, &sh, &w64);
+    const bool one128 = dim <= (int64_t)kMaxThreads * kMaxRows &&
+                        sweep_supported(d, (int)dim, K, true, ctx->lds_per_block, &sh, &w128);
+    if (!one64 || !one128) {
+      Split& sp = p->split;
+      std::string why;
+      if (!plan_split(ops, dim, d, K, ctx->lds_per_block, ctx->num_cu, &sp, &why)) {
+        sp = Split{};
+        if (!one64 && !one128)
+          return fail(HG_ERR_UNSUPPORTED, "dimension " + std::to_string(dim) +
+                                              " does not fit one workgroup and " + why);
+      } else {
+        const size_t dl = (size_t)sp.d_loc, P = (size_t)sp.P, W = (size_t)d.W;
+        sp.vals_stride = (size_t)(K + 1) * W * dl;
+        sp.valk_stride = (size_t)std::max(K, 1) * kMaxDiagCtrl * dl;
+        sp.omega_stride = dl;
+        std::vector<double2> lv(P * sp.vals_stride, double2{0.0, 0.0});
+        std::vector<double2> lk(P * sp.valk_stride, double2{0.0, 0.0});
+        std::vector<double> lo(P * dl, 0.0);
+        for (int q = 0; q < sp.P; ++q)
+          for (int t = 0; t < sp.T; ++t)
+            for (int k = 0; k < sp.w[q]; ++k) {
+              const size_t l = (size_t)t * sp.seg + sp.h + k;
+              const size_t gi = (size_t)t * sp.L + sp.c0[q] + k;
+              for (int o = 0; o <= K; ++o)
+                for (size_t e2 = 0; e2 < W; ++e2)
+                  lv[q * sp.vals_stride + ((size_t)o * W + e2) * dl + l] = hv[((size_t)o * W + e2) * dim + gi];
+              for (int k2 = 0; k2 < K; ++k2)
+                for (int qq = 0; qq < kMaxDiagCtrl; ++qq)
+                  lk[q * sp.valk_stride + ((size_t)k2 * kMaxDiagCtrl + qq) * dl + l] =
+                      hk[((size_t)k2 * kMaxDiagCtrl + qq) * dim + gi];
+              if (omega_diag) lo[q * dl + l] = omega_diag[gi];
+            }
+        HG_HIP(hipMalloc(&sp.ops.vals, lv.size() * sizeof(double2)));
+        HG_HIP(hipMemcpy(sp.ops.vals, lv.data(), lv.size() * sizeof(double2), hipMemcpyHostToDevice));
+        HG_HIP(hipMalloc(&sp.ops.valk, lk.size() * sizeof(double2)));
+        HG_HIP(hipMemcpy(sp.ops.valk, lk.data(), lk.size() * sizeof(double2), hipMemcpyHostToDevice));
+        if (omega_diag) {
+          HG_HIP(hipMalloc(&sp.ops.omega, lo.size() * sizeof(double)));
+          HG_HIP(hipMemcpy(sp.ops.omega, lo.data(), lo.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
+      }
+    }
+  }
   *out = p.release();
   return HG_OK;
 }
@@ -383,8 +523,21 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Workspace {
   size_t theta, pnorm, sched, psiN, cold, ckpt, segbuf, ovl, ovt, gt, pen, gradp, drift, res;
   size_t mat, emat, blocks;  // dense path
+  size_t psi0_loc, tgt_loc, xbuf, xnrm, xflag, xerr;  // split columns
   size_t total;
 };
+
+// Workgroups per state column for this problem and precision: 1 when one
+// workgroup holds a column, else the problem's split (0 if neither works).
+static int parts_for(const hg_problem* p, bool c128) {
+  if (p->dense) return 1;
+  SweepShape sh{};
+  std::string why;
+  if (p->dim <= (int64_t)kMaxThreads * kMaxRows &&
+      sweep_supported(p->ops, (int)p->dim, p->n_ctrl, c128, p->ctx->lds_per_block, &sh, &why))
+    return 1;
+  return p->split.P > 1 ? p->split.P : 0;
+}
 
 static DenseShape dense_shape(const hg_problem* p, int B, int N, int S, bool c128) {
   DenseShape sh{};
@@ -400,10 +553,13 @@ static DenseShape dense_shape(const hg_problem* p, int B, int N, int S, bool c12
   return sh;
 }
 
-static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128, int ckpt_every,
+static Workspace layout(const hg_problem* p, int B, int N, int S_true, bool c128, int ckpt_every,
                         bool integrated) {
   const size_t cs = c128 ? 16 : 8;
-  const size_t d = (size_t)p->dim, K = (size_t)p->n_ctrl;
+  const int parts = std::max(parts_for(p, c128), 1);
+  // a split column is P local columns of d_loc rows each
+  const size_t d = parts > 1 ? (size_t)p->split.d_loc : (size_t)p->dim, K = (size_t)p->n_ctrl;
+  const int S = S_true * parts;
   Workspace w{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -412,7 +568,7 @@ static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128, int
     return at;
   };
   w.theta = take((size_t)B * N * 8);
-  w.pnorm = take((size_t)B * S * 8);
+  w.pnorm = take((size_t)B * S_true * 8);
   w.sched = take((size_t)2 * B * N * 4);
   const bool dn = p->dense;
   w.psiN = take(dn ? 0 : (size_t)B * S * d * cs);
@@ -428,6 +584,15 @@ static Workspace layout(const hg_problem* p, int B, int N, int S, bool c128, int
   w.gradp = take(dn ? 0 : (size_t)B * S * std::max<size_t>(K, 1) * N * 8);
   w.drift = take((size_t)B * S * 8);
   w.res = take((size_t)B * 8 * 8);
+  if (parts > 1) {
+    const Split& sp = p->split;
+    w.psi0_loc = take((size_t)B * S * d * 16);
+    w.tgt_loc = take((size_t)B * S * d * 16);
+    w.xbuf = take((size_t)B * S * 4 * sp.T * std::max(sp.h, 1) * 64);
+    w.xnrm = take((size_t)B * S * kMaxParts * 8);
+    w.xflag = take((size_t)B * S * 4);
+    w.xerr = take(4);
+  }
   if (dn) {
     const DenseShape sh = dense_shape(p, B, N, S, c128);
     const size_t rs = cs / 2, Mp = 2 * (size_t)sh.dp;
@@ -475,9 +640,9 @@ hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* d, size_t* 
 
 // Bytes of host staging one evaluation needs: norms, state norms, schedule,
 // result scalars and drifts.
-static size_t host_stage_bytes(int B, int N, int S) {
+static size_t host_stage_bytes(int B, int N, int S, int parts) {
   return (size_t)B * N * 8 + (size_t)B * S * 8 + (size_t)2 * B * N * 4 + (size_t)B * 8 * 8 +
-         (size_t)B * S * 8;
+         (size_t)B * S * parts * 8 + 8;
 }
 
 // The evaluation proper, on a workspace `ws` laid out by layout() and a host
@@ -504,6 +669,8 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
   int32_t* h_sched = (int32_t*)(h_pnorm + (size_t)B * S);
   double* h_res = (double*)(h_sched + (size_t)2 * B * N);
   double* h_drift = h_res + (size_t)B * 8;
+  const int parts = std::max(sh.parts, 1);
+  uint32_t* h_xerr = (uint32_t*)(h_drift + (size_t)B * S * parts);
 
   double* d_theta = (double*)(ws + w.theta);
   double* d_pnorm = (double*)(ws + w.pnorm);
@@ -595,13 +762,26 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
     db.grad = grad;
     for (int i = 0; i < 3; ++i) db.ev[i] = bf.ev[i];
     HG_HIP(launch_dense_sweep(p->dops, dense_shape(p, B, N, S, c128), db, sp, h_m, h_s, hs));
+  } else if (parts > 1) {
+    SplitBuffers x{};
+    x.psi0_loc = (double2*)(ws + w.psi0_loc);
+    x.tgt_loc = (double2*)(ws + w.tgt_loc);
+    x.xbuf = (unsigned char*)(ws + w.xbuf);
+    x.xnrm = (double*)(ws + w.xnrm);
+    x.xflag = (uint32_t*)(ws + w.xflag);
+    x.xerr = (uint32_t*)(ws + w.xerr);
+    HG_HIP(launch_split_sweep(p->split, sh, bf, x, sp, S, hs));
+    HG_HIP(hipMemcpyAsync(h_xerr, x.xerr, 4, hipMemcpyDeviceToHost, hs));
   } else {
     HG_HIP(launch_sweep(p->ops, sh, bf, sp, hs));
   }
   HG_HIP(hipMemcpyAsync(h_res, bf.res, (size_t)B * 8 * 8, hipMemcpyDeviceToHost, hs));
-  HG_HIP(hipMemcpyAsync(h_drift, bf.drift, (size_t)B * S * 8, hipMemcpyDeviceToHost, hs));
+  HG_HIP(hipMemcpyAsync(h_drift, bf.drift, (size_t)B * S * parts * 8, hipMemcpyDeviceToHost, hs));
   HG_HIP(hipStreamSynchronize(hs));
   drain.armed = false;
+  if (parts > 1 && *h_xerr != 0)
+    return fail(HG_ERR_DEVICE, "split-column sweep: a workgroup waited too long for the halo rows "
+                               "of its neighbour (are other kernels holding the compute units?)");
   float ms_f = 0.f, ms_b = 0.f;
   if (d->flags & HG_FLAG_TIMING) {
     HG_HIP(hipEventElapsedTime(&ms_f, bf.ev[0], bf.ev[1]));
@@ -625,7 +805,15 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
       if (!d->schedule)
         mb = std::max(mb, error_bound(h_theta[i], h_m[i], h_s[i], p->sigma, std::ldexp(1.0, -53)));
     }
-    for (int h = 0; h < S; ++h) dr = std::max(dr, h_drift[(size_t)b * S + h]);
+    for (int h = 0; h < S; ++h) {
+      // a split column's parts hold disjoint rows: combine their partial drifts
+      double d2 = 0.0;
+      for (int q = 0; q < parts; ++q) {
+        const double x = h_drift[((size_t)b * S + h) * parts + q];
+        d2 += x * x;
+      }
+      dr = std::max(dr, parts > 1 ? std::sqrt(d2) : h_drift[(size_t)b * S + h]);
+    }
     r.sum_mu = mu;
     r.max_theta = mt;
     r.max_bound = mb;
@@ -649,9 +837,27 @@ static hg_status eval_prepare(hg_problem* p, const hg_eval_desc* d, hg_result* r
   HG_HIP(hipSetDevice(p->ctx->device));
   std::string why;
   *sh = SweepShape{};
-  if (!p->dense &&
-      !sweep_supported(p->ops, (int)p->dim, K, c128, p->ctx->lds_per_block, sh, &why))
-    return fail(HG_ERR_UNSUPPORTED, why);
+  sh->parts = 1;
+  if (!p->dense) {
+    const int parts = parts_for(p, c128);
+    if (parts == 1) {
+      if (!sweep_supported(p->ops, (int)p->dim, K, c128, p->ctx->lds_per_block, sh, &why))
+        return fail(HG_ERR_UNSUPPORTED, why);
+      sh->parts = 1;
+    } else if (parts > 1) {
+      if (!split_supported(p->split, K, c128, p->ctx->lds_per_block, p->ctx->num_cu, sh, &why))
+        return fail(HG_ERR_UNSUPPORTED, why);
+      sh->parts = parts;
+      // the parts of a column wait on each other: all workgroups must be resident at once
+      if ((int64_t)B * S * parts > (int64_t)p->ctx->num_cu)
+        return fail(HG_ERR_UNSUPPORTED,
+                    "a split evaluation needs n_batch * n_states * " + std::to_string(parts) +
+                        " <= " + std::to_string(p->ctx->num_cu) + " co-resident workgroups");
+    } else {
+      sweep_supported(p->ops, (int)p->dim, K, c128, p->ctx->lds_per_block, sh, &why);
+      return fail(HG_ERR_UNSUPPORTED, why);
+    }
+  }
   sh->n_steps = N;
   sh->n_states = S;
   sh->n_batch = B;
@@ -674,7 +880,7 @@ hg_status eval_on_buffers(hg_problem* p, const hg_eval_desc* d, hg_result* resul
     return fail(HG_ERR_OUT_OF_MEMORY, "the evaluation needs " + std::to_string(w.total) +
                                           " bytes of device workspace; " +
                                           std::to_string(ws_bytes) + " are available");
-  const size_t hb = host_stage_bytes(d->n_batch, d->n_steps, d->n_states);
+  const size_t hb = host_stage_bytes(d->n_batch, d->n_steps, d->n_states, std::max(sh.parts, 1));
   if (hb > hbuf_bytes)
     return fail(HG_ERR_OUT_OF_MEMORY, "the evaluation needs " + std::to_string(hb) +
                                           " bytes of host staging; " + std::to_string(hbuf_bytes) +
@@ -717,7 +923,7 @@ static hg_status eval_impl(hg_problem* p, const hg_eval_desc* d, hg_result* resu
       if (p) (void)hipFreeAsync(p, s);
     }
   } guard{ws, hs};
-  const size_t hbytes = host_stage_bytes(d->n_batch, d->n_steps, d->n_states);
+  const size_t hbytes = host_stage_bytes(d->n_batch, d->n_steps, d->n_states, std::max(sh.parts, 1));
   if (t_stage.n < hbytes) {
     if (t_stage.p) HG_HIP(hipHostFree(t_stage.p));
     t_stage.p = nullptr;

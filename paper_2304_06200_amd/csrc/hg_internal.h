@@ -39,6 +39,27 @@ struct DevOps {
 
 constexpr int kDenseMaxDim = 8192;  // dense storage: (K+1) dp^2 complex128 on the device
 
+// A state column too long for one workgroup, split over P co-resident
+// workgroups.  The rows are blocks of L (row r = t L + c, t < T): every union
+// offset is either a multiple of L (it keeps c) or at most h in size and stays
+// inside its block.  Part p owns c in [c0[p], c0[p] + w[p]) of every block, so
+// only the h rows at each edge of its c-range couple to a neighbouring part.
+// Locally a part stores, per block t, a segment of `seg` rows: h halo rows
+// (copies of the left neighbour's edge), its own w[p] rows, h halo rows (the
+// right neighbour's edge) and padding; local offsets map q L -> q seg.  The
+// local operators are DIA arrays over the T * seg local rows whose halo and
+// padding rows are zero, so a part runs the ordinary sweep kernels on them and
+// refreshes its halo rows from its neighbours after every Taylor term.
+constexpr int kMaxParts = 16;
+constexpr int kMaxDimSplit = 65536;
+struct Split {
+  int P = 1;                      // 1: no split
+  int L = 0, T = 0, h = 0, seg = 0, d_loc = 0;
+  int w[kMaxParts] = {0}, c0[kMaxParts] = {0};
+  DevOps ops;                     // local operators: arrays hold P parts back to back
+  size_t vals_stride = 0, valk_stride = 0, omega_stride = 0;  // elements per part
+};
+
 // Operators on the device as dense matrices (problems created with dense
 // storage): H[o][i][j], o = 0 (H0) then 1..K, row-major, dp = dim rounded up to
 // 64, zero outside dim x dim.
@@ -66,6 +87,7 @@ struct hg_problem {
   bool dense = false;              // dense storage: the MFMA path runs, not the DIA kernels
   int64_t dp = 0;                  // padded dimension of the dense matrices
   hg::DenseOps dops;
+  hg::Split split;                 // column split for dimensions beyond one workgroup
   ~hg_problem();                   // frees the device arrays (also on a failed creation)
 };
 
@@ -103,6 +125,7 @@ struct SweepShape {
   int fwd_rows_per_thread, fwd_threads;  // the forward kernel's own launch shape
   size_t lds_fwd, lds_bwd;
   bool c128;
+  int parts;                             // workgroups per state column (1 = no split)
 };
 hipError_t launch_step_norms(const DevOps& ops, int dim, int K, const double* u, int nb,
                              int N, double dt, double* theta, hipStream_t st);
@@ -138,6 +161,22 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
                      SweepShape* shape, std::string* why);
 hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuffers& b,
                         const SweepParams& p, hipStream_t st);
+
+// Split-column sweeps (see Split).  The launch shape of one part's local
+// problem, or false with the reason; the sweep itself with split buffers.
+bool split_supported(const Split& sp, int K, bool c128, size_t lds_limit, int num_cu,
+                     SweepShape* shape, std::string* why);
+struct SplitBuffers {
+  double2* psi0_loc;               // [B][S*P][d_loc] gathered initial states (zero halo)
+  double2* tgt_loc;                // [B][S*P][d_loc] gathered targets
+  unsigned char* xbuf;             // exchange rows: [B][S*P][2][2][T h][64 bytes]
+  double* xnrm;                    // [B][S*P][kMaxParts] partial norms (ring)
+  uint32_t* xflag;                 // [B][S*P] exchange sequence numbers
+  uint32_t* xerr;                  // [1] set when a wait timed out
+};
+hipError_t launch_split_sweep(const Split& sp, const SweepShape& sh, const SweepBuffers& b,
+                              const SplitBuffers& x, const SweepParams& p, int S_true,
+                              hipStream_t st);
 
 // Dense path (dense_kernels.hip).
 struct DenseShape {

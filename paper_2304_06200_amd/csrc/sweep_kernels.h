@@ -60,7 +60,21 @@ struct SweepArgs {
   double* drift;         // [B][S]
   double* res;           // [B][8]
   double dt, w_fid, w_pen, w_int;
+  // Split columns (P > 1): local column h = h_true * P + part, S = S_true * P;
+  // vals/valk/omega hold P parts back to back (strides psv, psk, pso).
+  int P, St;             // parts per column (1: no split), true number of states
+  int xT, xh, xseg, xrows;  // blocks, halo rows per side, local rows per block, xT * xh
+  int xw[kMaxParts];     // own rows per block of each part
+  size_t psv, psk, pso;
+  unsigned char* xbuf;   // [B][S][2 slots][2 sides][xrows][kXRowBytes] edge rows
+  double* xnrm;          // [B][S][kMaxParts] partial norms (ring of slots)
+  uint32_t* xflag;       // [B][S] last exchange each local column has published
+  uint32_t* xerr;        // [1] non-zero once a wait timed out
+  uint64_t xwait;        // longest wait, ticks of the 100 MHz real-time counter
 };
+
+constexpr int kXRowBytes = 64;                   // bytes reserved per exchanged row
+constexpr uint64_t kXWaitTicks = 2000000000ull;  // default longest wait: 20 s at 100 MHz
 
 template <typename R>
 __device__ __forceinline__ void cmac(cx<R>& acc, const cx<R>& a, const cx<R>& b) {
@@ -117,7 +131,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
 // Rows of B_n = -i (dt/s) (H_0 + sum_k u_k H_k) on the union diagonals,
 // assembled in FP64 and rounded once to the working precision.
 template <typename R, int RPT, int W>
-__device__ __forceinline__ void assemble_B(const SweepArgs& a, const double* ub, int n,
+__device__ __forceinline__ void assemble_B(const SweepArgs& a, const double2* vals,
+                                           const double* ub, int n,
                                            const int (&row)[RPT], const bool (&ok)[RPT],
                                            double cs, cx<R> (&bv)[RPT][W]) {
   const int d = a.d;
@@ -128,12 +143,12 @@ __device__ __forceinline__ void assemble_B(const SweepArgs& a, const double* ub,
     for (int e = 0; e < W; ++e) {
       double hr = 0.0, hi = 0.0;
       if (e < a.W && ok[r]) {
-        const double2 v0 = a.vals[(size_t)e * d + i];
+        const double2 v0 = vals[(size_t)e * d + i];
         hr = v0.x;
         hi = v0.y;
         for (int k = 0; k < a.K; ++k) {
           const double c = ub[(size_t)k * a.N + n];
-          const double2 v = a.vals[((size_t)(k + 1) * a.W + e) * d + i];
+          const double2 v = vals[((size_t)(k + 1) * a.W + e) * d + i];
           hr = fma(c, v.x, hr);
           hi = fma(c, v.y, hi);
         }
@@ -146,7 +161,7 @@ __device__ __forceinline__ void assemble_B(const SweepArgs& a, const double* ub,
 
 // E_k/s = -i (dt/s) H_k on the control's own diagonals (FP64 -> working precision).
 template <typename R, int RPT, int WK>
-__device__ __forceinline__ void load_E(const SweepArgs& a, int k, bool active,
+__device__ __forceinline__ void load_E(const SweepArgs& a, const double2* valk, int k, bool active,
                                        const int (&row)[RPT], const bool (&ok)[RPT], double cs,
                                        cx<R> (&ek)[RPT][WK]) {
 #pragma unroll
@@ -156,7 +171,7 @@ __device__ __forceinline__ void load_E(const SweepArgs& a, int k, bool active,
     for (int q = 0; q < WK; ++q) {
       double er = 0.0, ei = 0.0;
       if (active && q < a.WK[k] && ok[r]) {
-        const double2 v = a.valk[((size_t)k * kMaxDiagCtrl + q) * a.d + i];
+        const double2 v = valk[((size_t)k * kMaxDiagCtrl + q) * a.d + i];
         er = cs * v.y;
         ei = -cs * v.x;
       }
@@ -252,6 +267,121 @@ __device__ __forceinline__ T lds_ld(uint32_t off) {
 template <typename T>
 __device__ __forceinline__ void lds_st(uint32_t off, const T& v) {
   *reinterpret_cast<T*>(hg_smem + off) = v;
+}
+
+// ------------------------------------------------------- split columns ------
+// A column split over P workgroups (one per part, local columns h*P + part)
+// refreshes the halo rows of every Taylor term from its neighbours.  Wave 0 of
+// each workgroup copies its edge rows to global memory, publishes the exchange
+// number with a release store at device scope, waits (bounded) until both
+// neighbours have published it, and copies their edge rows into its halo rows;
+// a barrier then hands the block to every wave.  Edge rows are double buffered
+// by exchange parity: a neighbour can be at most one exchange ahead.  A wait
+// that exceeds a.xwait (or sees another workgroup's timeout) sets the error
+// flag and stops all further waiting of this workgroup, which then finishes
+// its sweep with meaningless numbers; the host reports the error.
+struct XState {
+  int b, hp, part;   // evaluation, local column, part
+  uint32_t seq;      // exchanges so far (the same in every part of a column)
+  int abort;         // (wave 0) a wait failed: no more waiting
+};
+
+__device__ __forceinline__ bool xwait(const SweepArgs& a, int col, uint32_t seq, uint64_t t0) {
+  while (__hip_atomic_load(&a.xflag[col], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < seq) {
+    if (__hip_atomic_load(a.xerr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+    if (__builtin_amdgcn_s_memrealtime() - t0 > a.xwait) {
+      __hip_atomic_store(a.xerr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+template <typename R, int LR, int V>
+__device__ __forceinline__ void halo_exchange(const SweepArgs& a, uint32_t base, uint32_t buf,
+                                           XState& xs) {
+  using L = Blk<R, LR, V>;
+  using Row = typename L::Row;
+  static_assert(L::NP * L::RB <= kXRowBytes, "exchange row too wide");
+  if (a.xh == 0) return;  // parts share no rows: nothing to exchange
+  xs.seq += 1u;
+  if (threadIdx.x < 64 && !xs.abort) {
+    const int lane = threadIdx.x;
+    const int hh = a.xh, seg = a.xseg, w = a.xw[xs.part], ne = a.xrows, d = a.d;
+    const uint32_t slot = xs.seq & 1u;
+    const int col = xs.b * a.S + xs.hp;
+    auto xrow = [&](int c, uint32_t sl, int side, int r) {
+      return a.xbuf + ((((size_t)c * 2 + sl) * 2 + side) * ne + r) * kXRowBytes;
+    };
+    // side 0: the first hh own rows of every block, side 1: the last hh
+    for (int i = lane; i < 2 * ne * L::NP; i += 64) {
+      const int pl = i % L::NP, r = (i / L::NP) % ne, side = i / (L::NP * ne);
+      const int t = r / hh, k = r % hh;
+      const uint32_t lrow = (uint32_t)(t * seg + (side == 0 ? hh + k : w + k));
+      const Row v = lds_ld<Row>(base + buf + lrow * L::RB + pl * L::ps(d));
+      *reinterpret_cast<Row*>(xrow(col, slot, side, r) + pl * L::RB) = v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) __hip_atomic_store(&a.xflag[col], xs.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    if (lane == 0) {
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      if (xs.part > 0 && !xwait(a, col - 1, xs.seq, t0)) ok = 0;
+      if (ok && xs.part + 1 < a.P && !xwait(a, col + 1, xs.seq, t0)) ok = 0;
+    }
+    ok = __builtin_amdgcn_readfirstlane(ok);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!ok) {
+      xs.abort = 1;
+    } else {
+      // left neighbour's side 1 -> my low halo rows; right neighbour's side 0 -> my high halo rows
+      for (int i = lane; i < 2 * ne * L::NP; i += 64) {
+        const int pl = i % L::NP, r = (i / L::NP) % ne, side = i / (L::NP * ne);
+        const int t = r / hh, k = r % hh;
+        if (side == 0 ? xs.part == 0 : xs.part + 1 == a.P) continue;
+        const unsigned char* src = side == 0 ? xrow(col - 1, slot, 1, r) : xrow(col + 1, slot, 0, r);
+        const uint32_t lrow = (uint32_t)(t * seg + (side == 0 ? k : hh + w + k));
+        lds_st(base + buf + lrow * L::RB + pl * L::ps(d), *reinterpret_cast<const Row*>(src + pl * L::RB));
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Sum of one value over the P parts of this column, in part order (so every
+// part gets the same bits).  All threads call it; the result goes to all.
+__device__ __forceinline__ double part_allsum(const SweepArgs& a, double v, XState& xs, double* red) {
+  xs.seq += 1u;
+  if (threadIdx.x < 64 && !xs.abort) {
+    const int lane = threadIdx.x;
+    const int col = xs.b * a.S + xs.hp, first = col - xs.part;
+    const uint32_t slot = xs.seq % (uint32_t)kMaxParts;
+    if (lane == 0) {
+      a.xnrm[(size_t)col * kMaxParts + slot] = v;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&a.xflag[col], xs.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int ok = 1;
+    if (lane == 0) {
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      for (int q = 0; q < a.P && ok; ++q)
+        if (q != xs.part && !xwait(a, first + q, xs.seq, t0)) ok = 0;
+    }
+    ok = __builtin_amdgcn_readfirstlane(ok);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!ok) {
+      xs.abort = 1;
+    } else if (lane == 0) {
+      double t = 0.0;
+      for (int q = 0; q < a.P; ++q) t += a.xnrm[(size_t)(first + q) * kMaxParts + slot];
+      red[60] = t;
+    }
+  }
+  __syncthreads();
+  const double t = red[60];
+  __syncthreads();
+  return xs.abort && threadIdx.x < 64 ? v : t;
 }
 
 // Tail-vector role of a wavefront (see taylor_block): kNotShared for a wave
@@ -446,14 +576,14 @@ __device__ __forceinline__ void tail_share(int tv, uint32_t base, const SweepArg
 // `base` is the byte offset of buffer 0, plane 0, row 0.  The term loop is
 // unrolled by two so the buffer being read is a compile-time choice.  Ends
 // with a barrier, so the block may be rewritten right away.
-template <typename R, int RPT, int W, int V, int WK, bool AUX, int LR = RPT>
+template <typename R, int RPT, int W, int V, int WK, bool AUX, int LR, bool SPLIT>
 __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, int g0,
                                              const uint32_t (&rowb)[RPT],
                                              const bool (&ok)[RPT], const bool (&sv)[RPT],
                                              int tv,
                                              const cx<R> (&bv)[RPT][W],
                                              const cx<R> (&ek)[V][RPT][WK], int m, int s, R sgn,
-                                             cx<R> (&acc)[RPT][V]) {
+                                             cx<R> (&acc)[RPT][V], XState& xs) {
   // A wavefront whose last row slab lies past the dimension runs the RPT-1 row
   // variant (wave-uniform choice, both variants fully unrolled).  The waves of
   // a shared tail slab (tv != kNotShared: four waves on different SIMDs) run
@@ -462,9 +592,11 @@ __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, 
   const bool full = tv == kNotShared ? sv[RPT - 1] : (V == 1 && tv == 0);
   const bool share = sizeof(R) == 4 && V > 1 && tv >= 0;
   constexpr int NRS = RPT > 1 ? RPT - 1 : 1;
+  using BL = Blk<R, LR, V>;
   for (int l = 0; l < s; ++l) {
     block_store<R, RPT, V, LR>(base, a.d, rowb, ok, tv, acc);
     __syncthreads();
+    if constexpr (SPLIT) halo_exchange<R, LR, V>(a, base, 0u, xs);
     for (int j = 1; j <= m; j += 2) {
       const R i1 = sgn * lds_ld<R>(kInvOff + j * (int)sizeof(R));
       if (full)
@@ -473,6 +605,7 @@ __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, 
         taylor_term<R, RPT, NRS, W, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, i1, acc);
       if (share) tail_share<R, RPT, W, V, WK, AUX, false, LR>(tv, base, a, g0, rowb, ok, bv, ek, i1, acc);
       __syncthreads();
+      if constexpr (SPLIT) halo_exchange<R, LR, V>(a, base, BL::bs(a.d), xs);
       if (j + 1 <= m) {
         const R i2 = sgn * lds_ld<R>(kInvOff + (j + 1) * (int)sizeof(R));
         if (full)
@@ -481,17 +614,20 @@ __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, 
           taylor_term<R, RPT, NRS, W, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, i2, acc);
         if (share) tail_share<R, RPT, W, V, WK, AUX, true, LR>(tv, base, a, g0, rowb, ok, bv, ek, i2, acc);
         __syncthreads();
+        if constexpr (SPLIT) halo_exchange<R, LR, V>(a, base, 0u, xs);
       }
     }
   }
 }
 
-template <typename R, int RPT>
-__device__ __forceinline__ void renormalise(cx<R> (&p)[RPT], double* red) {
+template <typename R, int RPT, bool SPLIT>
+__device__ __forceinline__ void renormalise(cx<R> (&p)[RPT], double* red, const SweepArgs& a,
+                                            XState& xs) {
   double nv[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) nv[0] += (double)p[r].re * p[r].re + (double)p[r].im * p[r].im;
   block_sum<1>(nv, red);
+  if constexpr (SPLIT) nv[0] = part_allsum(a, nv[0], xs, red);
   const R sc = (R)(1.0 / sqrt(nv[0]));
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
@@ -507,7 +643,7 @@ __device__ __forceinline__ void renormalise(cx<R> (&p)[RPT], double* red) {
 // TPB threads per workgroup; the LDS layout is that of LR = RPT*TPB/512 rows
 // per 512 threads, so the forward can run 1024 threads (4 waves per SIMD, to
 // hide the latency of its short, barrier-separated terms).
-template <typename R, int RPT, int W, int TPB>
+template <typename R, int RPT, int W, int TPB, bool SPLIT>
 __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
   using C = cx<R>;
   constexpr int LR = RPT * TPB / kMaxThreads;
@@ -516,6 +652,11 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
   const int d = a.d, tid = threadIdx.x, NT = blockDim.x;
   const int h = blockIdx.x, b = blockIdx.y;
   const size_t col0 = ((size_t)b * a.S + h) * d;
+  // a split column's part: its slice of the local operators
+  const int part = SPLIT ? h % a.P : 0;
+  const double2* vals = a.vals + (SPLIT ? (size_t)part * a.psv : 0);
+  const double* omega = a.omega ? a.omega + (SPLIT ? (size_t)part * a.pso : 0) : nullptr;
+  XState xs{b, h, part, 0u, 0};
   {
     uint32_t* z = reinterpret_cast<uint32_t*>(hg_smem + kRedBytes);
     for (int i = tid; i < L::bytes(d, a.halo) / 4; i += NT) z[i] = 0u;
@@ -553,21 +694,22 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
     const int m = a.msch[(size_t)b * a.N + n];
     const int s = a.ssch[(size_t)b * a.N + n];
     C bv[RPT][W];
-    assemble_B<R, RPT, W>(a, ub, n, row, ok, a.dt / (double)s, bv);
-    taylor_block<R, RPT, W, 1, 1, false, LR>(base, a, 0, rowb, ok, sv, kNotShared, bv, ek, m, s, (R)1, acc);
+    assemble_B<R, RPT, W>(a, vals, ub, n, row, ok, a.dt / (double)s, bv);
+    taylor_block<R, RPT, W, 1, 1, false, LR, SPLIT>(base, a, 0, rowb, ok, sv, kNotShared, bv, ek,
+                                                    m, s, (R)1, acc, xs);
     if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
       C p[RPT];
 #pragma unroll
       for (int r = 0; r < RPT; ++r) p[r] = acc[r][0];
-      renormalise<R, RPT>(p, red);
+      renormalise<R, RPT, SPLIT>(p, red, a, xs);
 #pragma unroll
       for (int r = 0; r < RPT; ++r) acc[r][0] = p[r];
     }
-    if (a.omega) {
+    if (omega) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
         if (ok[r])
-          pen += a.omega[row[r]] *
+          pen += omega[row[r]] *
                  ((double)acc[r][0].re * acc[r][0].re + (double)acc[r][0].im * acc[r][0].im);
     }
     if (ck && (n + 1) % CK == 0 && n + 1 < a.N)
@@ -624,7 +766,7 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
 // group) so that the (1+G)-vector double-buffered block fits in LDS.
 // TPB threads per workgroup, LDS layout of LR = RPT*TPB/512 rows per 512
 // threads (as in the forward kernel).
-template <typename R, int RPT, int W, int WK, int G, int TPB>
+template <typename R, int RPT, int W, int WK, int G, int TPB, bool SPLIT>
 __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   using C = cx<R>;
   constexpr int V2 = 1 + G;
@@ -635,6 +777,14 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   const int d = a.d, tid = threadIdx.x, NT = blockDim.x, K = a.K, N = a.N, S = a.S;
   const int h = blockIdx.x, b = blockIdx.y;
   const size_t col0 = ((size_t)b * S + h) * d;
+  // a split column's part: its slice of the local operators; the cost is
+  // normalised by the true number of states St (S counts local columns)
+  const int part = SPLIT ? h % a.P : 0;
+  const double2* vals = a.vals + (SPLIT ? (size_t)part * a.psv : 0);
+  const double2* valk = a.valk + (SPLIT ? (size_t)part * a.psk : 0);
+  const double* omega = a.omega ? a.omega + (SPLIT ? (size_t)part * a.pso : 0) : nullptr;
+  const int St = a.St;
+  XState xs{b, h, part, 0u, 0};
   {
     const int nb1 = L1::bytes(d, a.halo), nb2 = L2::bytes(d, a.halo);
     const int nb = nb1 > nb2 ? nb1 : nb2;
@@ -681,25 +831,25 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
     gim += a.ovl[((size_t)b * S + k) * 2 + 1];
     ptot += a.pen[(size_t)b * S + k];
   }
-  gre /= (double)S;
-  gim /= (double)S;
-  const double cpen = a.omega ? a.w_pen / ((double)N * S) : 0.0;
+  gre /= (double)St;
+  gim /= (double)St;
+  const double cpen = omega ? a.w_pen / ((double)N * St) : 0.0;
   // time-integrated infidelity: C3 (written by k_integrated) and the source
   // -(w_int/(N S)) g_n phi_T of every state psi_n, n = N..1 (App. A, Phi_T,n)
-  const double cint = a.ovt ? a.w_int / ((double)N * S) : 0.0;
+  const double cint = a.ovt ? a.w_int / ((double)N * St) : 0.0;
   if (h == 0 && tid == 0) {
     const double C1 = 1.0 - (gre * gre + gim * gim);
-    const double C2 = a.omega ? ptot / ((double)N * S) : 0.0;
+    const double C2 = omega ? ptot / ((double)N * St) : 0.0;
     const double C3 = a.ovt ? a.res[(size_t)b * 8 + 5] : 0.0;
     a.res[(size_t)b * 8 + 0] =
-        a.w_fid * C1 + (a.omega ? a.w_pen * C2 : 0.0) + (a.ovt ? a.w_int * C3 : 0.0);
+        a.w_fid * C1 + (omega ? a.w_pen * C2 : 0.0) + (a.ovt ? a.w_int * C3 : 0.0);
     a.res[(size_t)b * 8 + 1] = C1;
     a.res[(size_t)b * 8 + 2] = C2;
     a.res[(size_t)b * 8 + 3] = gre;
     a.res[(size_t)b * 8 + 4] = gim;
     a.res[(size_t)b * 8 + 5] = C3;
   }
-  const double fr = -(a.w_fid / S + cint) * gre, fi = -(a.w_fid / S + cint) * gim;
+  const double fr = -(a.w_fid / St + cint) * gre, fi = -(a.w_fid / St + cint) * gim;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const bool shared = tailw && r == RPT - 1;
@@ -712,7 +862,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
     rowb2[r] = (uint32_t)row[r] * L2::RB;
     const C p = psiN[col0 + row[r]];
     const double2 t = a.tgt[col0 + row[r]];
-    const double w = a.omega ? a.omega[row[r]] : 0.0;
+    const double w = omega ? omega[row[r]] : 0.0;
     pl[r][0] = own_psi[r] ? p : C{(R)0, (R)0};
     pl[r][1].re = own_lam[r] ? (R)(fr * t.x - fi * t.y + cpen * w * (double)p.re) : (R)0;
     pl[r][1].im = own_lam[r] ? (R)(fr * t.y + fi * t.x + cpen * w * (double)p.im) : (R)0;
@@ -756,15 +906,15 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       const int m = a.msch[(size_t)b * N + n];
       const int s = a.ssch[(size_t)b * N + n];
       C bv[RPT][W];
-      assemble_B<R, RPT, W>(a, ub, n, row, ok, a.dt / (double)s, bv);
+      assemble_B<R, RPT, W>(a, vals, ub, n, row, ok, a.dt / (double)s, bv);
       C ekf[1][RPT][1];
-      taylor_block<R, RPT, W, 1, 1, false, LR>(basef, a, 0, rowbf, ok, sv, tvp, bv, ekf, m, s,
-                                           (R)1, f);
+      taylor_block<R, RPT, W, 1, 1, false, LR, SPLIT>(basef, a, 0, rowbf, ok, sv, tvp, bv, ekf,
+                                                      m, s, (R)1, f, xs);
       if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
         C p[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) p[r] = f[r][0];
-        renormalise<R, RPT>(p, red);
+        renormalise<R, RPT, SPLIT>(p, red, a, xs);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) f[r][0] = p[r];
       }
@@ -775,20 +925,20 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
     const int s = a.ssch[(size_t)b * N + n];
     const double cs = a.dt / (double)s;
     C bv[RPT][W];
-    assemble_B<R, RPT, W>(a, ub, n, row, ok, cs, bv);
+    assemble_B<R, RPT, W>(a, vals, ub, n, row, ok, cs, bv);
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
       if (own_lam[r]) c_cur[opaque(row[r])] = pl[r][1];
 
     if (!ckpt) {
       // phase 1: psi and Lambda through (T_m(-B))^s together
-      taylor_block<R, RPT, W, 2, 1, false, LR>(base1, a, 0, rowb1, ok, sv, tv1, bv, ek1, m, s,
-                                           (R)-1, pl);
+      taylor_block<R, RPT, W, 2, 1, false, LR, SPLIT>(base1, a, 0, rowb1, ok, sv, tv1, bv, ek1,
+                                                      m, s, (R)-1, pl, xs);
       if (a.renorm_every > 0 && n % a.renorm_every == 0) {
         C p[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) p[r] = pl[r][0];
-        renormalise<R, RPT>(p, red);
+        renormalise<R, RPT, SPLIT>(p, red, a, xs);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) pl[r][0] = p[r];
       }
@@ -804,8 +954,8 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r) lm[r][0] = pl[r][1];
       C ekf[1][RPT][1];
-      taylor_block<R, RPT, W, 1, 1, false, LR>(basef, a, 0, rowbf, ok, sv, tvl, bv, ekf, m, s,
-                                           (R)-1, lm);
+      taylor_block<R, RPT, W, 1, 1, false, LR, SPLIT>(basef, a, 0, rowbf, ok, sv, tvl, bv, ekf,
+                                                      m, s, (R)-1, lm, xs);
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
         const int i = opaque(row[r]);
@@ -818,7 +968,8 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
     for (int g0 = 0; g0 < K; g0 += G) {
       C ek[V2][RPT][WK];
 #pragma unroll
-      for (int v = 1; v < V2; ++v) load_E<R, RPT, WK>(a, g0 + v - 1, g0 + v - 1 < K, row, ok, cs, ek[v]);
+      for (int v = 1; v < V2; ++v)
+        load_E<R, RPT, WK>(a, valk, g0 + v - 1, g0 + v - 1 < K, row, ok, cs, ek[v]);
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
 #pragma unroll
@@ -831,8 +982,8 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
 #pragma unroll
         for (int v = 1; v < V2; ++v) yx[r][v] = C{(R)0, (R)0};
       }
-      taylor_block<R, RPT, W, V2, WK, true, LR>(base2, a, g0, rowb2, ok, sv, tv2, bv, ek, m, s,
-                                            (R)1, yx);
+      taylor_block<R, RPT, W, V2, WK, true, LR, SPLIT>(base2, a, g0, rowb2, ok, sv, tv2, bv, ek,
+                                                       m, s, (R)1, yx, xs);
       double gv[G];
 #pragma unroll
       for (int v = 0; v < G; ++v) gv[v] = 0.0;
@@ -861,8 +1012,8 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       const C ps = ok[r] ? c_psi[i] : C{(R)0, (R)0};
       pl[r][0] = own_psi[r] ? ps : C{(R)0, (R)0};
       pl[r][1] = own_lam[r] ? c_lam[i] : C{(R)0, (R)0};
-      if (n >= 1 && own_lam[r] && (a.omega || a.ovt)) {
-        const double w = a.omega ? cpen * a.omega[i] : 0.0;
+      if (n >= 1 && own_lam[r] && (omega || a.ovt)) {
+        const double w = omega ? cpen * omega[i] : 0.0;
         double lr = (double)pl[r][1].re + w * (double)ps.re;
         double li = (double)pl[r][1].im + w * (double)ps.im;
         if (a.ovt) {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -85,7 +86,7 @@ __global__ void __launch_bounds__(256) k_reduce_grad(const double* gradp, double
 // every step (h ascending) and C3 = 1 - (1/N) sum_n |g_n|^2 per evaluation
 // (fixed-order block reduction), written to res[b][5].  One block per b.
 __global__ void __launch_bounds__(256) k_integrated(const double* ovt, double* gt, double* res,
-                                                    int S, int N) {
+                                                    int S, int St, int N) {
   __shared__ double red[256];
   const int b = blockIdx.x, tid = threadIdx.x;
   double acc = 0.0;
@@ -95,8 +96,8 @@ __global__ void __launch_bounds__(256) k_integrated(const double* ovt, double* g
       gr += ovt[(((size_t)b * S + h) * N + n) * 2 + 0];
       gi += ovt[(((size_t)b * S + h) * N + n) * 2 + 1];
     }
-    gr /= S;
-    gi /= S;
+    gr /= St;  // S local columns (a split column has several) of St states
+    gi /= St;
     gt[((size_t)b * N + n) * 2 + 0] = gr;
     gt[((size_t)b * N + n) * 2 + 1] = gi;
     acc += gr * gr + gi * gi;
@@ -111,7 +112,7 @@ __global__ void __launch_bounds__(256) k_integrated(const double* ovt, double* g
 }
 
 hipError_t launch_integrated(const SweepArgs& a, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_integrated, dim3(nb), dim3(256), 0, st, a.ovt, a.gt, a.res, a.S, a.N);
+  hipLaunchKernelGGL(k_integrated, dim3(nb), dim3(256), 0, st, a.ovt, a.gt, a.res, a.S, a.St, a.N);
   return hipGetLastError();
 }
 
@@ -260,6 +261,8 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
   a.w_fid = p.w_fid;
   a.w_pen = p.w_pen;
   a.w_int = p.w_int;
+  a.P = 1;
+  a.St = sh.n_states;
   hipError_t e;
   switch (width_template(ops.W)) {
     case 3: e = run_width_3(a, sh, st, bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr); break;
@@ -275,6 +278,194 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
     e = hipGetLastError();
   }
   return e;
+}
+
+// ------------------------------------------------------------ split columns --
+namespace {
+
+struct SplitLayout {
+  int P, L, T, h, seg, d_loc;
+  int w[kMaxParts], c0[kMaxParts];
+};
+
+// dst[b][h*P + q][l] = src[b][h][global row of local row l of part q], zero on
+// halo and padding rows.
+__global__ void __launch_bounds__(256) k_split_gather(const double2* __restrict__ src,
+                                                      double2* __restrict__ dst, int d, int St,
+                                                      SplitLayout sl) {
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  if (l >= sl.d_loc) return;
+  const int hp = blockIdx.y, b = blockIdx.z;
+  const int h = hp / sl.P, q = hp % sl.P;
+  const int t = l / sl.seg, k = l % sl.seg - sl.h;
+  double2 v = {0.0, 0.0};
+  if (k >= 0 && k < sl.w[q]) v = src[((size_t)b * St + h) * d + (size_t)t * sl.L + sl.c0[q] + k];
+  dst[((size_t)b * St * sl.P + hp) * sl.d_loc + l] = v;
+}
+
+__global__ void __launch_bounds__(256) k_fill_u32(uint32_t* p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+}  // namespace
+
+bool split_supported(const Split& sp, int K, bool c128, size_t lds_limit, int num_cu,
+                     SweepShape* sh, std::string* why) {
+  (void)num_cu;
+  if (sp.P < 2) {
+    *why = "no split";
+    return false;
+  }
+  if (K > kMaxCtrl) {
+    *why = "more than " + std::to_string(kMaxCtrl) + " controls";
+    return false;
+  }
+  if (sp.d_loc > 4 * kMaxThreads) {
+    *why = "a part of " + std::to_string(sp.d_loc) + " local rows exceeds the split kernels' " +
+           std::to_string(4 * kMaxThreads);
+    return false;
+  }
+  if (sp.ops.W > 9) {
+    *why = "the split kernels take at most 9 union diagonals";
+    return false;
+  }
+  for (int k = 0; k < K; ++k)
+    if (sp.ops.WK[k] > 2) {
+      *why = "the split kernels take controls of at most 2 diagonals";
+      return false;
+    }
+  const size_t cs = c128 ? 16 : 8;
+  const size_t fwd = lds_bytes(1, 4, sp.d_loc, sp.ops.halo, cs);
+  auto bwd_bytes = [&](int g) {
+    return std::max(lds_bytes(2, 4, sp.d_loc, sp.ops.halo, cs),
+                    lds_bytes(g + 1, 4, sp.d_loc, sp.ops.halo, cs));
+  };
+  int G = 1;
+  if (!c128 && K >= 2) G = (K % 3 == 0) ? 3 : (K % 2 == 0) ? 2 : (K >= 3 ? 3 : 2);
+  while (G > 1 && bwd_bytes(G) > lds_limit) --G;
+  if (fwd > lds_limit || bwd_bytes(G) > lds_limit) {
+    *why = "a part's term vectors do not fit in LDS";
+    return false;
+  }
+  sh->dim = sp.d_loc;
+  sh->n_ctrl = K;
+  sh->rows_per_thread = 4;
+  sh->threads = kMaxThreads;
+  sh->fwd_rows_per_thread = 4;
+  sh->fwd_threads = kMaxThreads;
+  sh->groups = G;
+  sh->lds_fwd = fwd;
+  sh->lds_bwd = bwd_bytes(G);
+  sh->c128 = c128;
+  sh->parts = sp.P;
+  return true;
+}
+
+hipError_t launch_split_sweep(const Split& sp, const SweepShape& sh0, const SweepBuffers& bf,
+                              const SplitBuffers& x, const SweepParams& p, int S_true,
+                              hipStream_t st) {
+  const int P = sp.P, B = sh0.n_batch, Sl = S_true * P;
+  SplitLayout sl{};
+  sl.P = P;
+  sl.L = sp.L;
+  sl.T = sp.T;
+  sl.h = sp.h;
+  sl.seg = sp.seg;
+  sl.d_loc = sp.d_loc;
+  for (int q = 0; q < kMaxParts; ++q) {
+    sl.w[q] = sp.w[q];
+    sl.c0[q] = sp.c0[q];
+  }
+  const int dim = sp.L * sp.T;
+  const dim3 gg((sp.d_loc + 255) / 256, Sl, B);
+  hipLaunchKernelGGL(k_split_gather, gg, dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(bf.psi0), x.psi0_loc, dim, S_true, sl);
+  hipLaunchKernelGGL(k_split_gather, gg, dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(bf.targets), x.tgt_loc, dim, S_true, sl);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, x.xerr, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+
+  SweepShape sh = sh0;
+  sh.n_states = Sl;
+  SweepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const DevOps& ops = sp.ops;
+  a.d = sp.d_loc;
+  a.K = sh.n_ctrl;
+  a.N = sh.n_steps;
+  a.S = Sl;
+  a.W = ops.W;
+  a.halo = ops.halo;
+  a.G = sh.groups;
+  a.renorm_every = p.renorm_every;
+  a.ckpt_every = p.ckpt_every;
+  for (int q = 0; q < kMaxDiag; ++q) a.off[q] = q < ops.W ? ops.off[q] : 0;
+  for (int k = 0; k < kMaxCtrl; ++k) {
+    a.WK[k] = k < sh.n_ctrl ? ops.WK[k] : 0;
+    for (int q = 0; q < kMaxDiagCtrl; ++q)
+      a.offk[k][q] = (k < sh.n_ctrl && q < ops.WK[k]) ? ops.offk[k][q] : 0;
+  }
+  a.vals = ops.vals;
+  a.valk = ops.valk;
+  a.omega = ops.omega;
+  a.u = bf.u;
+  a.msch = bf.m_sched;
+  a.ssch = bf.s_sched;
+  a.psi0 = x.psi0_loc;
+  a.tgt = x.tgt_loc;
+  a.psiN = bf.psiN;
+  a.cold = bf.cold;
+  a.ckpt = bf.ckpt;
+  a.segbuf = bf.segbuf;
+  a.ovl = bf.ovl;
+  a.ovt = bf.ovt;
+  a.gt = bf.gt;
+  a.pen = bf.pen;
+  a.gradp = bf.gradp;
+  a.drift = bf.drift;
+  a.res = bf.res;
+  a.dt = p.dt;
+  a.w_fid = p.w_fid;
+  a.w_pen = p.w_pen;
+  a.w_int = p.w_int;
+  a.P = P;
+  a.St = S_true;
+  a.xT = sp.T;
+  a.xh = sp.h;
+  a.xseg = sp.seg;
+  a.xrows = sp.T * std::max(sp.h, 1);
+  for (int q = 0; q < kMaxParts; ++q) a.xw[q] = sp.w[q];
+  a.psv = sp.vals_stride;
+  a.psk = sp.valk_stride;
+  a.pso = sp.omega_stride;
+  a.xbuf = x.xbuf;
+  a.xnrm = x.xnrm;
+  a.xflag = x.xflag;
+  a.xerr = x.xerr;
+  // longest wait for a neighbour; HG_SPLIT_WAIT_TICKS (100 MHz ticks) shortens
+  // it, which lets a test drive the timeout path with every kernel exiting normally
+  a.xwait = kXWaitTicks;
+  if (const char* env = std::getenv("HG_SPLIT_WAIT_TICKS")) {
+    char* end = nullptr;
+    const unsigned long long v = std::strtoull(env, &end, 10);
+    if (end && end != env) a.xwait = v;
+  }
+  e = run_split(a, sh, st, bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr);
+  if (e != hipSuccess) return e;
+  if (bf.grad && sh.n_ctrl > 0) {
+    const size_t total = (size_t)B * sh.n_ctrl * sh.n_steps;
+    hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       bf.gradp, bf.grad, Sl, sh.n_ctrl * sh.n_steps, B);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+  return hipGetLastError();
 }
 
 }  // namespace hg

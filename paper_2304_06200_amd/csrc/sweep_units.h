@@ -15,20 +15,26 @@ hipError_t run_width_13(const SweepArgs& a, const SweepShape& sh, hipStream_t st
 
 hipError_t launch_integrated(const SweepArgs& a, int nb, hipStream_t st);
 
+// Split-column sweep kernels (sweep_split.hip): 512 threads, 4 rows each,
+// union width template 5 or 9, controls of at most 2 diagonals.
+hipError_t run_split(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
+// Zero n counters on the stream (a kernel, so that graph capture records no memset).
+hipError_t launch_fill_u32(uint32_t* p, int n, hipStream_t st);
+
 template <typename R, int RPT, int W, int WK, int G>
 hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream_t st,
                              hipEvent_t* ev) {
-  auto fk = hg_forward<R, RPT, W, kMaxThreads>;
-  auto bk = hg_backward<R, RPT, W, WK, G, kMaxThreads>;
+  auto fk = hg_forward<R, RPT, W, kMaxThreads, false>;
+  auto bk = hg_backward<R, RPT, W, WK, G, kMaxThreads, false>;
   if constexpr (W <= 9 && RPT <= (W <= 5 ? 6 : 4)) {
     if (sh.fwd_threads > kMaxThreads) {
-      if (sh.fwd_rows_per_thread == 1) fk = hg_forward<R, 1, W, kWideThreads>;
-      else if (sh.fwd_rows_per_thread == 2) fk = hg_forward<R, 2, W, kWideThreads>;
-      else if constexpr (W <= 5) fk = hg_forward<R, 3, W, kWideThreads>;
+      if (sh.fwd_rows_per_thread == 1) fk = hg_forward<R, 1, W, kWideThreads, false>;
+      else if (sh.fwd_rows_per_thread == 2) fk = hg_forward<R, 2, W, kWideThreads, false>;
+      else if constexpr (W <= 5) fk = hg_forward<R, 3, W, kWideThreads, false>;
     }
   }
   if constexpr (sizeof(R) == 4 && WK <= 2 && (RPT <= 2 || (RPT == 3 && W <= 5 && G <= 2))) {
-    if (sh.threads > kMaxThreads) bk = hg_backward<R, RPT, W, WK, G, kWideThreads>;
+    if (sh.threads > kMaxThreads) bk = hg_backward<R, RPT, W, WK, G, kWideThreads, false>;
   }
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fk),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_fwd);

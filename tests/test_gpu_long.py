@@ -4,12 +4,12 @@ checkpointed-state variant (a state stored every 100 steps), complex64 and
 complex128, with the reconstruction drift and the device footprint of both
 variants reported.
 
-The full-size problem (cavity 1024, d = 8192) exceeds what one workgroup holds
-and is rejected with HG_ERR_UNSUPPORTED (tested below).  The sweep runs at
-cavity 256 (d = 2048), the largest size whose complex128 backward block fits in
-LDS, against the Taylor-discretised oracle evaluated offline
+Here the sweep runs at cavity 256 (d = 2048, one workgroup per column in both
+precisions) against the Taylor-discretised oracle evaluated offline
 (tests/golden/make_golden.py cfg5:d_c=256 --discrete, states stored, no
-reconstruction) with the oracle planner's schedule."""
+reconstruction) with the oracle planner's schedule.  The full size (cavity
+1024, d = 8192: columns split over several workgroups) is in test_gpu_split.py
+and test_gpu_cfg5.py."""
 import numpy as np
 import pytest
 
@@ -19,17 +19,6 @@ from workloads import make_config
 pytestmark = pytest.mark.gpu
 
 GOLDEN = "cfg5_t8c256_discrete"
-
-
-def test_full_size_rejected():
-    import paper_2304_06200_amd as hg
-    from paper_2304_06200_amd import _lib as L
-    p = make_config("cfg5", N=3)
-    log(f"[case] cfg5 full size d={p.dim}: expect UNSUPPORTED")
-    with pytest.raises(hg._lib.HGError) as e:
-        make_problem(p)
-    assert e.value.status == L.HG_ERR_UNSUPPORTED, str(e.value)
-    log(f"  {e.value}")
 
 
 @pytest.fixture(scope="module")
