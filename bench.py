@@ -38,10 +38,11 @@ def flops_per_term(nnz, nnz_ctrl, K):
     return fwd, bwd
 
 
-def run_precision(hg, prob, u, psi0, tg, p, dtype, steps, warmup, w_int=0.0):
+def run_precision(hg, prob, u, psi0, tg, p, dtype, steps, warmup, w_int=0.0, **extra):
     import numpy as np
     import torch
-    kw = dict(w_fid=p.w_fid, w_pen=p.w_pen, w_int=w_int, tau=p.tau, dtype=dtype, timing=True)
+    kw = dict(w_fid=p.w_fid, w_pen=p.w_pen, w_int=w_int, tau=p.tau, dtype=dtype, timing=True,
+              **extra)
     for w in range(warmup):
         hg.evaluate(prob, u, psi0, tg, p.dt, **kw)
         log(f"  warmup {w + 1}/{warmup} {dtype} done")
@@ -95,7 +96,8 @@ def serving(hg, ctx, dtype, n_req, inflight, budget, qps, seed=4):
     """cfg4 stream: n_req requests of transmon(3) x cavity(d_c) problems, d_c
     log-uniform in [8, 700], N in [200, 2000], S in [1, 8].  First all at once
     (saturated throughput), then Poisson arrivals at a fixed rate `qps` (the
-    same for both precisions); latency is submit-to-finish per request."""
+    same for both precisions) with spread backward sweeps (idle compute units
+    shorten each request); latency is submit-to-finish per request."""
     import numpy as np
     import torch
     from workloads.configs import serving_request, serving_stream
@@ -129,12 +131,45 @@ def serving(hg, ctx, dtype, n_req, inflight, budget, qps, seed=4):
         delay = t_next - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
-        hs.append(sv.submit(*dev[i][:1], *dev[i][1:], reqs[i].dt, **kw(reqs[i])))
+        hs.append(sv.submit(*dev[i][:1], *dev[i][1:], reqs[i].dt, spread=True, **kw(reqs[i])))
     lats = [sv.wait(h)[1] for h in hs]
     sv.close()
     st = hg.percentiles(lats)
     log(f"  serving {dtype}: at {rate:.2f} req/s p50 {st['p50_ms']:.0f} ms p99 {st['p99_ms']:.0f} ms")
-    return {"saturated_req_per_s": sat, "offered_req_per_s": rate, **st}
+    return {"saturated_req_per_s": sat, "offered_req_per_s": rate, "spread": True, **st}
+
+
+def cfg5_leg(hg, ctx, no_c128):
+    """transmon(8) x cavity(1024), d = 8192, N = 5000, S = 4: one evaluation
+    per precision and backward variant (reconstruction; checkpoints every 100
+    steps), with its time, drift and measured peak workspace."""
+    import torch
+    from workloads import make_config
+    p = make_config("cfg5")
+    prob = hg.Problem(ctx, p.H0, p.Hk, p.omega)
+    u = torch.tensor(p.u, dtype=torch.float64, device="cuda")
+    psi0 = torch.tensor(p.psi0, dtype=torch.complex128, device="cuda")
+    tg = torch.tensor(p.targets, dtype=torch.complex128, device="cuda")
+    out = {"workload": "cfg5: transmon(8) x cavity(1024), d=8192, K=4, N=5000, dt=0.2 ns, S=4, "
+                       "penalty on; columns split over several workgroups"}
+    for dtype in (["c64"] if no_c128 else ["c64", "c128"]):
+        out[dtype] = {}
+        for key, mode, C in (("reconstruct", "reconstruct", 0),
+                             ("checkpoint_every_100", "checkpoint", 100)):
+            log(f"[bench] cfg5 {dtype} {key}")
+            torch.cuda.synchronize()
+            hg.mem_pool_peak(ctx, reset=True)
+            t0 = time.perf_counter()
+            r = hg.evaluate(prob, u, psi0, tg, p.dt, w_fid=p.w_fid, w_pen=p.w_pen, tau=p.tau,
+                            dtype=dtype, mode=mode, ckpt_every=C, timing=True)
+            el = time.perf_counter() - t0
+            out[dtype][key] = {"seconds": el, "evals_per_s": 1.0 / el, "cost": float(r.cost[0]),
+                               "drift": float(r.drift[0]), "sum_mu": int(r.sum_mu[0]),
+                               "ms_forward": r.ms_forward, "ms_backward": r.ms_backward,
+                               "peak_workspace_bytes": hg.mem_pool_peak(ctx)}
+            log(f"[bench] cfg5 {dtype} {key}: {el:.1f} s, drift {r.drift[0]:.2e}, "
+                f"peak {out[dtype][key]['peak_workspace_bytes']} B")
+    return out
 
 
 def cpu_baseline(p_full, n_sample):
@@ -178,7 +213,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c128", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-inflight", type=int, default=32)
     ap.add_argument("--serve-qps", type=float, default=4.0)
     ap.add_argument("--no-serving", action="store_true")
@@ -186,6 +221,8 @@ def main():
                     help="skip the leg with the time-integrated infidelity term")
     ap.add_argument("--gate-batch", type=int, default=8,
                     help="concurrent evaluations of the dense-storage gate leg")
+    ap.add_argument("--no-cfg5", action="store_true",
+                    help="skip the d = 8192 leg (columns split over several workgroups)")
     ap.add_argument("--no-gate", action="store_true",
                     help="skip the full-basis gate leg (three coupled transmons)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -280,10 +317,17 @@ def main():
     streaming["note"] = ("bytes a streaming SpMM design would move; the sweep keeps its working set in "
                          "LDS and registers, so this exceeds the 8 TB/s HBM peak")
     line["streaming_model"] = streaming
-    # one evaluation alone (16 workgroups): its latency, next to the batched throughput
-    r1 = run_precision(hg, prob, u[:1], psi0, tg, p, "c64", 2, 1)
-    line["batch1_latency_ms"] = {"c64": r1["ms_per_step"], "concurrent_evals": 1}
-    log(f"[bench] c64 batch 1: {r1['ms_per_step']:.1f} ms per evaluation")
+    # one evaluation alone: its latency, next to the batched throughput; with
+    # spread, several workgroups share each column's backward sweep
+    lat = {"concurrent_evals": 1}
+    for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
+        r1 = run_precision(hg, prob, u[:1], psi0, tg, p, dtype, 2, 1)
+        r1s = run_precision(hg, prob, u[:1], psi0, tg, p, dtype, 2, 1, spread=True)
+        lat[dtype] = r1["ms_per_step"]
+        lat[dtype + "_spread"] = r1s["ms_per_step"]
+        log(f"[bench] {dtype} batch 1: {r1['ms_per_step']:.1f} ms per evaluation, "
+            f"{r1s['ms_per_step']:.1f} ms with spread")
+    line["batch1_latency_ms"] = lat
     # device memory of one evaluation (Table I): HG reconstruction keeps no state
     # history; checkpointing every step stores it (the stored-history comparator)
     from paper_2304_06200_amd import _lib as L
@@ -314,6 +358,8 @@ def main():
                    "measured as the high-water mark of the workspace pool (hipMemPoolAttrUsedMemHigh); "
                    "stored_history = checkpoint every step, i.e. every psi_n kept (Table I)")
     line["memory_per_eval_bytes"] = mem
+    if not args.no_cfg5:
+        line["cfg5"] = cfg5_leg(hg, ctx, args.no_c128)
     if not args.no_integrated:
         # the same workload with the time-integrated infidelity C3 added (App. A)
         log("[bench] c64 with the time-integrated infidelity term (w_int = 1)")

@@ -186,11 +186,18 @@ typedef struct {
   const int32_t* schedule;   /* NULL, or host [2][B][N]: frozen (m, s) per step
                                 (the planner is skipped; norms are still computed) */
   int32_t flags;             /* bit 0 (HG_FLAG_TIMING): time the sweep kernels with
-                                HIP events on `stream`, reported in hg_result */
+                                HIP events on `stream`, reported in hg_result;
+                                bit 1 (HG_FLAG_SPREAD): let several workgroups share
+                                one column's backward sweep when the batch leaves
+                                compute units idle (each repeats the reconstruction
+                                and co-state and takes a share of the controls):
+                                lower latency for small batches, more total work;
+                                results equal those without it to rounding */
   int32_t rule;              /* hg_plan_rule_t of the planner (0 = the paper's) */
 } hg_eval_desc;
 
 #define HG_FLAG_TIMING 1
+#define HG_FLAG_SPREAD 2
 
 typedef struct {
   double cost;               /* w_fid C1 + w_pen C2 + w_int C3 */

@@ -27,6 +27,7 @@ HG_ERR_UNSUPPORTED = 9
 HG_C64 = 0
 HG_C128 = 1
 HG_FLAG_TIMING = 1
+HG_FLAG_SPREAD = 2
 HG_MODE_RECONSTRUCT = 0
 HG_MODE_CHECKPOINT = 1
 HG_PLAN_SMALLEST_S, HG_PLAN_MIN_MU = 0, 1

@@ -140,7 +140,7 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
              renorm_every: Optional[int] = None, schedule: Optional[np.ndarray] = None,
              want_grad: bool = True, timing: bool = False, mode: str = "reconstruct",
              ckpt_every: int = 0, stream=None, rule: str = "smallest_s",
-             noalloc: bool = False, grad_out=None) -> EvalResult:
+             noalloc: bool = False, grad_out=None, spread: bool = False) -> EvalResult:
     """Cost and gradient of B amplitude sets.
 
     u        torch float64 device tensor (K, N) or (B, K, N)
@@ -155,6 +155,8 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
     noalloc  run through hg_eval_noalloc (the library's fixed scratch; no
              allocation in the call, one call at a time per device)
     grad_out optional preallocated float64 device tensor (B, K, N) for the gradient
+    spread   let several workgroups share a column's backward sweep when the
+             batch leaves compute units idle (lower latency, more total work)
     """
     torch = _torch()
     if u.dim() == 2:
@@ -192,7 +194,8 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
     mcode = {"reconstruct": L.HG_MODE_RECONSTRUCT, "checkpoint": L.HG_MODE_CHECKPOINT}[mode]
     desc = make_desc(N, B, dt, _ptr(u) if K > 0 else None, S, _ptr(psi0), _ptr(targets),
                      w_fid, w_pen, tau, code, renorm_every, sched_p, mode=mcode,
-                     ckpt_every=ckpt_every, flags=L.HG_FLAG_TIMING if timing else 0,
+                     ckpt_every=ckpt_every,
+                     flags=(L.HG_FLAG_TIMING if timing else 0) | (L.HG_FLAG_SPREAD if spread else 0),
                      w_int=w_int, rule=RULES[rule])
     if grad_out is not None:
         if grad_out.shape != (B, K, N) or grad_out.dtype != torch.float64 or not grad_out.is_contiguous():

@@ -554,7 +554,7 @@ static DenseShape dense_shape(const hg_problem* p, int B, int N, int S, bool c12
 }
 
 static Workspace layout(const hg_problem* p, int B, int N, int S_true, bool c128, int ckpt_every,
-                        bool integrated) {
+                        bool integrated, int Q = 1) {
   const size_t cs = c128 ? 16 : 8;
   const int parts = std::max(parts_for(p, c128), 1);
   // a split column is P local columns of d_loc rows each
@@ -572,11 +572,11 @@ static Workspace layout(const hg_problem* p, int B, int N, int S_true, bool c128
   w.sched = take((size_t)2 * B * N * 4);
   const bool dn = p->dense;
   w.psiN = take(dn ? 0 : (size_t)B * S * d * cs);
-  w.cold = take(dn ? 0 : (size_t)B * S * 3 * d * cs);
+  w.cold = take(dn ? 0 : (size_t)B * S * Q * 3 * d * cs);
   const size_t C = ckpt_every > 0 ? (size_t)std::min(ckpt_every, N) : 0;
   const size_t nseg = ckpt_every > 0 ? ((size_t)N + ckpt_every - 1) / ckpt_every : 0;
   w.ckpt = take((size_t)B * S * nseg * d * cs);
-  w.segbuf = take((size_t)B * S * C * d * cs);
+  w.segbuf = take((size_t)B * S * Q * C * d * cs);
   w.ovl = take((size_t)B * S * 16);
   w.ovt = take(integrated ? (size_t)B * S * N * 16 : 0);
   w.gt = take(integrated ? (size_t)B * N * 16 : 0);
@@ -628,13 +628,18 @@ static hg_status check_desc(const hg_problem* p, const hg_eval_desc* d) {
   return HG_OK;
 }
 
+static hg_status shape_for(const hg_problem* p, const hg_eval_desc* d, SweepShape* sh);
+
 hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* d, size_t* bytes) {
   hg_status st = check_desc(p, d);
   if (st != HG_OK) return st;
   if (!bytes) return fail(HG_ERR_INVALID_ARG, "bytes is NULL");
+  SweepShape sh{};
+  sh.spread = 1;
+  if (shape_for(p, d, &sh) != HG_OK) sh.spread = 1;  // the evaluation itself reports it
   *bytes = layout(p, d->n_batch, d->n_steps, d->n_states, d->dtype == HG_C128,
                   d->mode == HG_MODE_CHECKPOINT ? d->ckpt_every : 0,
-                  d->w_int != 0.0).total;
+                  d->w_int != 0.0, sh.spread).total;
   return HG_OK;
 }
 
@@ -825,19 +830,47 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
 }
 
 
-// Checks, launch shape and buffer sizes of one evaluation (shared by the
-// entry points that bring their own memory).
-static hg_status eval_prepare(hg_problem* p, const hg_eval_desc* d, hg_result* results,
-                              SweepShape* sh, Workspace* w) {
-  hg_status st = check_desc(p, d);
-  if (st != HG_OK) return st;
-  if (!results) return fail(HG_ERR_INVALID_ARG, "results is NULL");
+// With HG_FLAG_SPREAD: the control group size and the number of backward
+// workgroups per column that minimise the estimated backward time when the
+// batch's B*S columns leave compute units idle.  Per Taylor term, phase 1
+// costs 2 products with the union operator; a phase-2 pass with g controls
+// costs 1 + g of them plus g control products (relative cost e).  Larger g
+// wins ties (less repeated work).
+static void choose_spread(const hg_problem* p, const hg_eval_desc* d, SweepShape* sh) {
+  sh->spread = 1;
+  const int K = p->n_ctrl;
+  if (!(d->flags & HG_FLAG_SPREAD) || p->dense || sh->parts > 1 || K < 2) return;
+  const int budget = p->ctx->num_cu / std::max(1, d->n_batch * d->n_states);
+  if (budget < 2) return;
+  double e = 0.0;
+  for (int k = 0; k < K; ++k) e += (double)p->nnz_ctrl[k];
+  e = e / K / std::max<double>((double)p->nnz, 1.0);
+  double best = 1e300;
+  int bg = sh->groups, bq = 1;
+  for (int g = sh->groups; g >= 1; --g) {
+    const int groups = (K + g - 1) / g;
+    const int q = std::min(groups, budget);
+    const int passes = (groups + q - 1) / q;
+    const double cost = 2.0 + passes * (1.0 + g * (1.0 + e));
+    if (cost < best - 1e-9) {
+      best = cost;
+      bg = g;
+      bq = q;
+    }
+  }
+  sh->groups = bg;
+  sh->spread = bq;
+}
+
+// Launch shape of one evaluation: one workgroup per column, the problem's
+// split layout, or the dense path; then the optional spread of the backward.
+static hg_status shape_for(const hg_problem* p, const hg_eval_desc* d, SweepShape* sh) {
   const int B = d->n_batch, N = d->n_steps, S = d->n_states, K = p->n_ctrl;
   const bool c128 = d->dtype == HG_C128;
-  HG_HIP(hipSetDevice(p->ctx->device));
   std::string why;
   *sh = SweepShape{};
   sh->parts = 1;
+  sh->spread = 1;
   if (!p->dense) {
     const int parts = parts_for(p, c128);
     if (parts == 1) {
@@ -857,12 +890,28 @@ static hg_status eval_prepare(hg_problem* p, const hg_eval_desc* d, hg_result* r
       sweep_supported(p->ops, (int)p->dim, K, c128, p->ctx->lds_per_block, sh, &why);
       return fail(HG_ERR_UNSUPPORTED, why);
     }
+    sh->spread = 1;
+    choose_spread(p, d, sh);
   }
   sh->n_steps = N;
   sh->n_states = S;
   sh->n_batch = B;
+  return HG_OK;
+}
+
+// Checks, launch shape and buffer sizes of one evaluation (shared by the
+// entry points that bring their own memory).
+static hg_status eval_prepare(hg_problem* p, const hg_eval_desc* d, hg_result* results,
+                              SweepShape* sh, Workspace* w) {
+  hg_status st = check_desc(p, d);
+  if (st != HG_OK) return st;
+  if (!results) return fail(HG_ERR_INVALID_ARG, "results is NULL");
+  HG_HIP(hipSetDevice(p->ctx->device));
+  if ((st = shape_for(p, d, sh)) != HG_OK) return st;
+  const int N = d->n_steps;
   const int ck = d->mode == HG_MODE_CHECKPOINT ? std::min(d->ckpt_every, N) : 0;
-  *w = layout(p, B, N, S, c128, ck, d->w_int != 0.0);
+  *w = layout(p, d->n_batch, N, d->n_states, d->dtype == HG_C128, ck, d->w_int != 0.0,
+              sh->spread);
   return HG_OK;
 }
 

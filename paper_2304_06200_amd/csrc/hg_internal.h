@@ -126,6 +126,7 @@ struct SweepShape {
   size_t lds_fwd, lds_bwd;
   bool c128;
   int parts;                             // workgroups per state column (1 = no split)
+  int spread;                            // backward workgroups sharing a column's controls
 };
 hipError_t launch_step_norms(const DevOps& ops, int dim, int K, const double* u, int nb,
                              int N, double dt, double* theta, hipStream_t st);

@@ -49,9 +49,9 @@ struct SweepArgs {
   const double2* psi0;   // [B][S][d]
   const double2* tgt;    // [B][S][d]
   void* psiN;            // [B][S][d] (working precision)
-  void* cold;            // [B][S][3][d] (working precision)
+  void* cold;            // [B][S][Q][3][d] (working precision; Q = gridDim.z of the backward)
   void* ckpt;            // [B][S][ceil(N/C)][d] checkpoints psi_0, psi_C, ... (checkpoint variant)
-  void* segbuf;          // [B][S][C][d] states of the segment being swept back
+  void* segbuf;          // [B][S][Q][C][d] states of the segment being swept back
   double* ovl;           // [B][S][2]
   double* ovt;           // [B][S][N][2] overlap after each step, or null (no C3 term)
   double* gt;            // [B][N][2] g_n = (1/S) sum_h ovt (filled between the sweeps)
@@ -796,7 +796,14 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   const uint32_t base1 = kRedBytes + a.halo * L1::RB;
   const uint32_t base2 = kRedBytes + a.halo * L2::RB;
 
-  C* cold = reinterpret_cast<C*>(a.cold) + ((size_t)b * S + h) * 3 * d;
+  // Several workgroups may share a column (gridDim.z = Q): each repeats the
+  // reconstruction and co-state (phase 1) and takes every Q-th group of G
+  // controls in phase 2, so a column's backward sweep spreads over Q compute
+  // units.  The arithmetic of each control is the same whichever workgroup
+  // runs it.  Rarely touched per-row vectors and checkpoint segments are per
+  // workgroup; only z = 0 writes the cost parts and the drift.
+  const int z = blockIdx.z, Q = gridDim.z;
+  C* cold = reinterpret_cast<C*>(a.cold) + (((size_t)b * S + h) * Q + z) * 3 * d;
   C* const c_psi = cold;          // psi_{n-1}
   C* const c_lam = cold + d;      // propagated co-state
   C* const c_cur = cold + 2 * d;  // Lambda_n (for the overlaps)
@@ -837,7 +844,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   // time-integrated infidelity: C3 (written by k_integrated) and the source
   // -(w_int/(N S)) g_n phi_T of every state psi_n, n = N..1 (App. A, Phi_T,n)
   const double cint = a.ovt ? a.w_int / ((double)N * St) : 0.0;
-  if (h == 0 && tid == 0) {
+  if (h == 0 && z == 0 && tid == 0) {
     const double C1 = 1.0 - (gre * gre + gim * gim);
     const double C2 = omega ? ptot / ((double)N * St) : 0.0;
     const double C3 = a.ovt ? a.res[(size_t)b * 8 + 5] : 0.0;
@@ -891,7 +898,8 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   for (int r = 0; r < RPT; ++r) rowbf[r] = (uint32_t)row[r] * LF::RB;
   const C* ckb = ckpt ? reinterpret_cast<const C*>(a.ckpt) + ((size_t)b * S + h) * (size_t)nseg * d
                       : nullptr;
-  C* seg = ckpt ? reinterpret_cast<C*>(a.segbuf) + ((size_t)b * S + h) * (size_t)CK * d : nullptr;
+  C* seg = ckpt ? reinterpret_cast<C*>(a.segbuf) + (((size_t)b * S + h) * Q + z) * (size_t)CK * d
+                 : nullptr;
   for (int sg = nseg - 1; sg >= 0; --sg) {
   const int n0 = ckpt ? sg * CK : 0;
   const int n1 = ckpt ? (n0 + CK < N ? n0 + CK : N) : N;
@@ -964,8 +972,8 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       }
     }
 
-    // phase 2: auxiliary actions, G controls per pass
-    for (int g0 = 0; g0 < K; g0 += G) {
+    // phase 2: auxiliary actions, G controls per pass (every Q-th pass here)
+    for (int g0 = z * G; g0 < K; g0 += Q * G) {
       C ek[V2][RPT][WK];
 #pragma unroll
       for (int v = 1; v < V2; ++v)
@@ -1040,7 +1048,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       dv[0] += dr * dr + di * di;
     }
   block_sum<1>(dv, red);
-  if (tid == 0) a.drift[(size_t)b * S + h] = sqrt(dv[0]);
+  if (tid == 0 && z == 0) a.drift[(size_t)b * S + h] = sqrt(dv[0]);
 }
 
 }  // namespace hg

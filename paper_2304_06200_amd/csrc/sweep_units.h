@@ -49,7 +49,8 @@ hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream
   if (e != hipSuccess) return e;
   if (a.ovt && (e = launch_integrated(a, sh.n_batch, st)) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(bk, grid, block, sh.lds_bwd, st, a);
+  const dim3 bgrid(sh.n_states, sh.n_batch, sh.spread > 1 ? sh.spread : 1);
+  hipLaunchKernelGGL(bk, bgrid, block, sh.lds_bwd, st, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev) e = hipEventRecord(ev[2], st);

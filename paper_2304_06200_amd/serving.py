@@ -30,7 +30,7 @@ class Server:
     def submit(self, problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.0,
                w_pen: float = 0.0, w_int: float = 0.0, tau: float = 1e-12, dtype: str = "c64",
                renorm_every: Optional[int] = None, mode: str = "reconstruct",
-               ckpt_every: int = 0) -> Handle:
+               ckpt_every: int = 0, spread: bool = False) -> Handle:
         """u: float64 device tensor (K, N) or (B, K, N); psi0, targets: complex128
         device tensors (S, d) or (B, S, d).  Returns a handle for wait().
 
@@ -56,7 +56,8 @@ class Server:
         mcode = {"reconstruct": L.HG_MODE_RECONSTRUCT, "checkpoint": L.HG_MODE_CHECKPOINT}[mode]
         desc = make_desc(N, B, dt, int(u.data_ptr()) if K > 0 else None, S, int(psi0.data_ptr()),
                          int(targets.data_ptr()), w_fid, w_pen, tau, code, renorm_every, None,
-                         mode=mcode, ckpt_every=ckpt_every, w_int=w_int)
+                         mode=mcode, ckpt_every=ckpt_every, w_int=w_int,
+                         flags=L.HG_FLAG_SPREAD if spread else 0)
         grad = torch.empty((B, K, N), dtype=torch.float64, device=u.device) if K > 0 else None
         res = (L.hg_result * B)()
         rid = L.hg_server_submit(self.handle, problem.handle, desc, res,

@@ -181,3 +181,29 @@ def test_error_paths():
     # the evaluation still works after the errors
     r = hg.evaluate(prob, u, psi0, tg, p.dt)
     assert np.isfinite(r.cost[0])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_spread_backward(dtype):
+    """HG_FLAG_SPREAD (several workgroups per column in the backward sweep,
+    each repeating phase 1 and taking a share of the controls): parity with
+    the oracle, agreement with the plain launch to rounding, and bitwise
+    repeatability; cfg3 structure (6 controls) with a 20-level cavity, one
+    evaluation, and a batch of 3."""
+    import paper_2304_06200_amd as hg
+    p = make_config("cfg3", N=30, d_c=20)
+    prob = make_problem(p)
+    ref = _oracle(p)
+    log(f"[case] spread backward cfg3c20 {dtype}")
+    a = run(p, dtype, prob=prob, spread=True)
+    b = run(p, dtype, prob=prob)
+    c = run(p, dtype, prob=prob, spread=True)
+    assert_parity(a, ref, dtype, label="spread")
+    ga, gb = a.grad[0].cpu().numpy(), b.grad[0].cpu().numpy()
+    assert np.linalg.norm(ga - gb) <= (1e-13 if dtype == "c128" else 1e-6) * np.linalg.norm(gb)
+    assert a.cost[0] == c.cost[0] and np.array_equal(ga, c.grad[0].cpu().numpy())
+    from workloads.configs import _amps
+    u3 = np.stack([p.u] + [_amps(np.random.default_rng(300 + i), p.n_ctrl, p.n_steps)
+                           for i in range(2)])
+    r3 = run(p, dtype, prob=prob, batch_u=u3, spread=True)
+    assert r3.cost[0] == a.cost[0] or abs(r3.cost[0] - a.cost[0]) <= 1e-12 * abs(a.cost[0])

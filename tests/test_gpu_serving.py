@@ -174,3 +174,20 @@ def test_submit_waits_for_inputs_on_caller_stream():
         for b in range(3):
             assert r.cost[b] == alone.cost[b], (p.name, b)
         assert np.array_equal(r.grad.cpu().numpy(), alone.grad.cpu().numpy()), p.name
+
+
+def test_spread_requests_equal_spread_alone():
+    """Requests submitted with spread backward sweeps equal the same spread
+    evaluation run alone (bitwise), while other requests run beside them."""
+    import paper_2304_06200_amd as hg
+    reqs = _stream(8, seed=21)
+    sv = hg.Server(context(), hbm_budget_bytes=4 << 30, max_inflight=4)
+    log("[case] serving 8 requests, spread on every other one, c64")
+    hs = [sv.submit(_problem(p), *_dev(p), p.dt, spread=(i % 2 == 0), **_kw(p, "c64"))
+          for i, p in enumerate(reqs)]
+    out = [sv.wait(h) for h in hs]
+    sv.close()
+    for i, (p, (r, _, _)) in enumerate(zip(reqs, out)):
+        alone = hg.evaluate(_problem(p), *_dev(p), p.dt, spread=(i % 2 == 0), **_kw(p, "c64"))
+        assert r.cost[0] == alone.cost[0], p.name
+        assert np.array_equal(r.grad.cpu().numpy(), alone.grad.cpu().numpy()), p.name
