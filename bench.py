@@ -410,6 +410,16 @@ def main():
             log(f"[bench] gate3 dense {dtype}: {dense[dtype]['value']:.2f} evals/s, "
                 f"{tf:.1f} TFLOP/s over the sweep ({100 * tf / PEAK_MFMA_TFLOPS[dtype]:.0f}% of MFMA peak)")
         line["gate"]["dense"] = dense
+        # the same gate by diagonalising H_n per step (App. F): Jacobi eigensolver
+        # in FP64, library GEMMs for the basis changes
+        diag = {"method": "diagonalisation (App. F)", "concurrent_evals": Bg}
+        for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
+            rd = run_precision(hg, probd, ugb_t, pg0, tgg, pg, dtype, max(args.steps, 3),
+                               args.warmup, method="diag")
+            diag[dtype] = {"value": Bg / (rd["ms_per_step"] * 1e-3), "unit": "evals/s",
+                           "ms_per_step": rd["ms_per_step"]}
+            log(f"[bench] gate3 diag {dtype}: {diag[dtype]['value']:.2f} evals/s")
+        line["gate"]["diag"] = diag
     if not args.no_serving:
         log(f"[bench] serving stream: {args.serve_requests} requests, {args.serve_inflight} slots")
         budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)

@@ -66,6 +66,17 @@ typedef enum { HG_MODE_RECONSTRUCT = 0, HG_MODE_CHECKPOINT = 1 } hg_mode;
  * products mu = m s (ties: smaller s), the alternative Sec. III.B mentions and
  * sets aside because the minimisation costs more than it saves there. */
 typedef enum { HG_PLAN_SMALLEST_S = 0, HG_PLAN_MIN_MU = 1 } hg_plan_rule_t;
+/* How each step's propagator and its derivative are applied:
+ *   TAYLOR  the Taylor scaling-and-squaring action with the auxiliary block
+ *           matrix (Sec. III.B), any storage;
+ *   DIAG    diagonalisation of H_n per step (App. F, eqs. matrix dia and
+ *           propagator der): U_n = V e^{-i dt D} V^H, dU_n/du_k from the
+ *           divided differences of exp in the eigenbasis; dense storage only;
+ *   AUTO    dense storage: DIAG when the Taylor products would cost more
+ *           (Sec. V: Taylor ~ mu d^2 S per step against d^3 + d^2 S), i.e. when
+ *           mean mu * S >= c (d + S), c = 40 (complex128) or 200 (complex64)
+ *           from the measured crossover; else TAYLOR. */
+typedef enum { HG_METHOD_TAYLOR = 0, HG_METHOD_DIAG = 1, HG_METHOD_AUTO = 2 } hg_method_t;
 
 /* A host CSR matrix of complex128 values (dim x dim). */
 typedef struct {
@@ -194,6 +205,7 @@ typedef struct {
                                 lower latency for small batches, more total work;
                                 results equal those without it to rounding */
   int32_t rule;              /* hg_plan_rule_t of the planner (0 = the paper's) */
+  int32_t method;            /* hg_method_t (0 = Taylor); DIAG/AUTO need dense storage */
 } hg_eval_desc;
 
 #define HG_FLAG_TIMING 1

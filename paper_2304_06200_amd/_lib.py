@@ -31,6 +31,7 @@ HG_FLAG_SPREAD = 2
 HG_MODE_RECONSTRUCT = 0
 HG_MODE_CHECKPOINT = 1
 HG_PLAN_SMALLEST_S, HG_PLAN_MIN_MU = 0, 1
+HG_METHOD_TAYLOR, HG_METHOD_DIAG, HG_METHOD_AUTO = 0, 1, 2
 
 
 class HGError(RuntimeError):
@@ -59,7 +60,8 @@ class hg_eval_desc(C.Structure):
                 ("targets", C.c_void_p), ("w_fid", C.c_double), ("w_pen", C.c_double),
                 ("w_int", C.c_double), ("tau", C.c_double), ("dtype", C.c_int), ("mode", C.c_int),
                 ("ckpt_every", C.c_int32), ("renorm_every", C.c_int32),
-                ("schedule", C.POINTER(C.c_int32)), ("flags", C.c_int32), ("rule", C.c_int32)]
+                ("schedule", C.POINTER(C.c_int32)), ("flags", C.c_int32), ("rule", C.c_int32),
+                ("method", C.c_int32)]
 
 
 class hg_result(C.Structure):

@@ -109,7 +109,7 @@ def _ptr(t) -> int:
 
 def make_desc(n_steps, n_batch, dt, u, n_states, psi0, targets, w_fid, w_pen, tau, dtype,
               renorm_every, schedule=None, mode=L.HG_MODE_RECONSTRUCT, ckpt_every=0, flags=0,
-              w_int=0.0, rule=L.HG_PLAN_SMALLEST_S):
+              w_int=0.0, rule=L.HG_PLAN_SMALLEST_S, method=L.HG_METHOD_TAYLOR):
     d = L.hg_eval_desc()
     d.n_steps = n_steps
     d.n_batch = n_batch
@@ -129,10 +129,12 @@ def make_desc(n_steps, n_batch, dt, u, n_states, psi0, targets, w_fid, w_pen, ta
     d.schedule = schedule
     d.flags = flags
     d.rule = rule
+    d.method = method
     return d
 
 
 RULES = {"smallest_s": L.HG_PLAN_SMALLEST_S, "min_mu": L.HG_PLAN_MIN_MU}
+METHODS = {"taylor": L.HG_METHOD_TAYLOR, "diag": L.HG_METHOD_DIAG, "auto": L.HG_METHOD_AUTO}
 
 
 def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.0,
@@ -140,7 +142,8 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
              renorm_every: Optional[int] = None, schedule: Optional[np.ndarray] = None,
              want_grad: bool = True, timing: bool = False, mode: str = "reconstruct",
              ckpt_every: int = 0, stream=None, rule: str = "smallest_s",
-             noalloc: bool = False, grad_out=None, spread: bool = False) -> EvalResult:
+             noalloc: bool = False, grad_out=None, spread: bool = False,
+             method: str = "taylor") -> EvalResult:
     """Cost and gradient of B amplitude sets.
 
     u        torch float64 device tensor (K, N) or (B, K, N)
@@ -157,6 +160,7 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
     grad_out optional preallocated float64 device tensor (B, K, N) for the gradient
     spread   let several workgroups share a column's backward sweep when the
              batch leaves compute units idle (lower latency, more total work)
+    method   "taylor", "diag" (diagonalise H_n per step; dense storage) or "auto"
     """
     torch = _torch()
     if u.dim() == 2:
@@ -196,7 +200,7 @@ def evaluate(problem: Problem, u, psi0, targets, dt: float, *, w_fid: float = 1.
                      w_fid, w_pen, tau, code, renorm_every, sched_p, mode=mcode,
                      ckpt_every=ckpt_every,
                      flags=(L.HG_FLAG_TIMING if timing else 0) | (L.HG_FLAG_SPREAD if spread else 0),
-                     w_int=w_int, rule=RULES[rule])
+                     w_int=w_int, rule=RULES[rule], method=METHODS[method])
     if grad_out is not None:
         if grad_out.shape != (B, K, N) or grad_out.dtype != torch.float64 or not grad_out.is_contiguous():
             raise ValueError("grad_out must be a contiguous float64 tensor of shape (B, K, N)")

@@ -520,10 +520,18 @@ hg_status hg_step_norms(hg_problem* p, const double* u, int32_t n_batch, int32_t
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// HG_METHOD_AUTO: diagonalise when mean(mu) * S >= c (d + S).  The constants
+// come from the measured crossover on the three-transmon gate (d = S = 216 and
+// 512): the Jacobi eigensolver runs in FP64 for both precisions while the
+// complex64 Taylor products run twice as fast as the complex128 ones.
+constexpr double kAutoDiagC128 = 40.0;
+constexpr double kAutoDiagC64 = 200.0;
+
 struct Workspace {
   size_t theta, pnorm, sched, psiN, cold, ckpt, segbuf, ovl, ovt, gt, pen, gradp, drift, res;
   size_t mat, emat, blocks;  // dense path
   size_t psi0_loc, tgt_loc, xbuf, xnrm, xflag, xerr;  // split columns
+  size_t diag;                                         // diagonalisation method
   size_t total;
 };
 
@@ -554,7 +562,7 @@ static DenseShape dense_shape(const hg_problem* p, int B, int N, int S, bool c12
 }
 
 static Workspace layout(const hg_problem* p, int B, int N, int S_true, bool c128, int ckpt_every,
-                        bool integrated, int Q = 1) {
+                        bool integrated, int Q = 1, int method = HG_METHOD_TAYLOR) {
   const size_t cs = c128 ? 16 : 8;
   const int parts = std::max(parts_for(p, c128), 1);
   // a split column is P local columns of d_loc rows each
@@ -595,10 +603,13 @@ static Workspace layout(const hg_problem* p, int B, int N, int S_true, bool c128
   }
   if (dn) {
     const DenseShape sh = dense_shape(p, B, N, S, c128);
-    const size_t rs = cs / 2, Mp = 2 * (size_t)sh.dp;
-    w.mat = take((size_t)B * Mp * Mp * rs);
-    w.emat = take((size_t)B * K * Mp * Mp * rs);
-    w.blocks = take(dense_block_elems(sh) * rs);
+    if (method != HG_METHOD_DIAG) {  // Taylor products on the matrix cores (AUTO may take either)
+      const size_t rs = cs / 2, Mp = 2 * (size_t)sh.dp;
+      w.mat = take((size_t)B * Mp * Mp * rs);
+      w.emat = take((size_t)B * K * Mp * Mp * rs);
+      w.blocks = take(dense_block_elems(sh) * rs);
+    }
+    if (method != HG_METHOD_TAYLOR) w.diag = take(diag_work_bytes(sh));
   }
   w.total = o;
   return w;
@@ -621,6 +632,11 @@ static hg_status check_desc(const hg_problem* p, const hg_eval_desc* d) {
   if (d->renorm_every < 0) return fail(HG_ERR_INVALID_ARG, "renorm_every must be >= 0");
   if (d->rule != HG_PLAN_SMALLEST_S && d->rule != HG_PLAN_MIN_MU)
     return fail(HG_ERR_INVALID_ARG, "unknown planner rule");
+  if (d->method != HG_METHOD_TAYLOR && d->method != HG_METHOD_DIAG && d->method != HG_METHOD_AUTO)
+    return fail(HG_ERR_INVALID_ARG, "unknown method");
+  if (d->method == HG_METHOD_DIAG && !p->dense)
+    return fail(HG_ERR_UNSUPPORTED, "the diagonalisation method needs dense operator storage "
+                                    "(hg_problem_create_dense)");
   if ((p->n_ctrl > 0 && !d->u) || !d->psi0 || !d->targets)
     return fail(HG_ERR_INVALID_ARG, "NULL device array");
   if (p->dense && d->mode != HG_MODE_RECONSTRUCT)
@@ -639,7 +655,7 @@ hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* d, size_t* 
   if (shape_for(p, d, &sh) != HG_OK) sh.spread = 1;  // the evaluation itself reports it
   *bytes = layout(p, d->n_batch, d->n_steps, d->n_states, d->dtype == HG_C128,
                   d->mode == HG_MODE_CHECKPOINT ? d->ckpt_every : 0,
-                  d->w_int != 0.0, sh.spread).total;
+                  d->w_int != 0.0, sh.spread, p->dense ? d->method : HG_METHOD_TAYLOR).total;
   return HG_OK;
 }
 
@@ -647,7 +663,7 @@ hg_status hg_eval_footprint(const hg_problem* p, const hg_eval_desc* d, size_t* 
 // result scalars and drifts.
 static size_t host_stage_bytes(int B, int N, int S, int parts) {
   return (size_t)B * N * 8 + (size_t)B * S * 8 + (size_t)2 * B * N * 4 + (size_t)B * 8 * 8 +
-         (size_t)B * S * parts * 8 + 8;
+         (size_t)B * S * parts * 8 + 8 + (size_t)B * 8;
 }
 
 // The evaluation proper, on a workspace `ws` laid out by layout() and a host
@@ -676,6 +692,7 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
   double* h_drift = h_res + (size_t)B * 8;
   const int parts = std::max(sh.parts, 1);
   uint32_t* h_xerr = (uint32_t*)(h_drift + (size_t)B * S * parts);
+  int* h_done = (int*)(h_xerr + 2);
 
   double* d_theta = (double*)(ws + w.theta);
   double* d_pnorm = (double*)(ws + w.pnorm);
@@ -702,7 +719,11 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
       return fail(HG_ERR_NONFINITE, "amplitudes of step " + std::to_string(i % N) + " are not finite");
   int32_t* h_m = h_sched;
   int32_t* h_s = h_sched + (size_t)B * N;
-  if (d->schedule) {
+  const bool diag_only = p->dense && d->method == HG_METHOD_DIAG;
+  if (diag_only) {
+    // no Taylor products: no schedule (sum_mu and the bound are reported as 0)
+    for (int64_t i = 0; i < (int64_t)B * N; ++i) h_m[i] = h_s[i] = 0;
+  } else if (d->schedule) {
     for (int64_t i = 0; i < (int64_t)B * N; ++i) {
       h_m[i] = d->schedule[i];
       h_s[i] = d->schedule[(size_t)B * N + i];
@@ -718,6 +739,15 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
     if (st != HG_OK) return st;
   }
   HG_HIP(hipMemcpyAsync(d_sched, h_sched, (size_t)2 * B * N * 4, hipMemcpyHostToDevice, hs));
+  bool use_diag = diag_only;
+  if (p->dense && d->method == HG_METHOD_AUTO) {
+    // Sec. V: the Taylor products cost ~ mu d^2 S per step, diagonalisation
+    // ~ d^3 + d^2 S; take the diagonalisation when mean mu * S >= c (d + S)
+    double mu = 0.0;
+    for (int64_t i = 0; i < (int64_t)B * N; ++i) mu += (double)h_m[i] * h_s[i];
+    mu /= (double)B * N;
+    use_diag = mu * S >= (c128 ? kAutoDiagC128 : kAutoDiagC64) * ((double)p->dim + S);
+  }
 
   SweepBuffers bf{};
   bf.u = u_dev;
@@ -748,7 +778,23 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
   if (d->flags & HG_FLAG_TIMING)
     for (int i = 0; i < 3; ++i) HG_HIP(hipEventCreate(&bf.ev[i]));
   SweepParams sp{d->dt, d->w_fid, d->w_pen, d->w_int, d->renorm_every, ck};
-  if (p->dense) {
+  if (p->dense && use_diag) {
+    DiagBuffers db{};
+    db.u = u_dev;
+    db.psi0 = d->psi0;
+    db.targets = d->targets;
+    db.work = ws + w.diag;
+    db.h_done = h_done;
+    db.pen = bf.pen;
+    db.ovl = bf.ovl;
+    db.ovt = bf.ovt;
+    db.gt = bf.gt;
+    db.drift = bf.drift;
+    db.res = bf.res;
+    db.grad = grad;
+    for (int i = 0; i < 3; ++i) db.ev[i] = bf.ev[i];
+    HG_HIP(launch_diag_sweep(p->ctx->device, p->dops, dense_shape(p, B, N, S, c128), db, sp, hs));
+  } else if (p->dense) {
     DenseBuffers db{};
     db.u = u_dev;
     db.m_sched = bf.m_sched;
@@ -805,9 +851,9 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
     double mt = 0.0, mb = 0.0, dr = 0.0;
     for (int n = 0; n < N; ++n) {
       const size_t i = (size_t)b * N + n;
-      mu += (int64_t)h_m[i] * h_s[i];
+      if (!use_diag) mu += (int64_t)h_m[i] * h_s[i];
       mt = std::max(mt, h_theta[i]);
-      if (!d->schedule)
+      if (!d->schedule && !use_diag)
         mb = std::max(mb, error_bound(h_theta[i], h_m[i], h_s[i], p->sigma, std::ldexp(1.0, -53)));
     }
     for (int h = 0; h < S; ++h) {
@@ -911,7 +957,7 @@ static hg_status eval_prepare(hg_problem* p, const hg_eval_desc* d, hg_result* r
   const int N = d->n_steps;
   const int ck = d->mode == HG_MODE_CHECKPOINT ? std::min(d->ckpt_every, N) : 0;
   *w = layout(p, d->n_batch, N, d->n_states, d->dtype == HG_C128, ck, d->w_int != 0.0,
-              sh->spread);
+              sh->spread, p->dense ? d->method : HG_METHOD_TAYLOR);
   return HG_OK;
 }
 
@@ -925,6 +971,9 @@ hg_status eval_on_buffers(hg_problem* p, const hg_eval_desc* d, hg_result* resul
   Workspace w;
   hg_status st = eval_prepare(p, d, results, &sh, &w);
   if (st != HG_OK) return st;
+  if (p->dense && d->method != HG_METHOD_TAYLOR)
+    return fail(HG_ERR_UNSUPPORTED, "caller-provided memory: the diagonalisation method's library "
+                                    "GEMMs may allocate; use hg_eval");
   if (w.total > ws_bytes)
     return fail(HG_ERR_OUT_OF_MEMORY, "the evaluation needs " + std::to_string(w.total) +
                                           " bytes of device workspace; " +

@@ -204,6 +204,26 @@ struct DenseBuffers {
   hipEvent_t ev[3];
 };
 size_t dense_block_elems(const DenseShape& sh);
+
+// Matrix-diagonalisation variant for dense operators (diag.hip, App. F).
+struct DiagBuffers {
+  const double* u;
+  const double* psi0;              // [B][S][dim] complex128
+  const double* targets;           // [B][S][dim] complex128
+  void* work;                      // diag_work_bytes(shape)
+  int* h_done;                     // host [B]: convergence flags of the eigensolver
+  double* pen;                     // [B][S]
+  double* ovl;                     // [B][S][2]
+  double* ovt;                     // [B][S][N][2] or null (w_int == 0)
+  double* gt;                      // [B][N][2] (with ovt)
+  double* drift;                   // [B][S]
+  double* res;                     // [B][8]
+  double* grad;                    // [B][K][N] or nullptr
+  hipEvent_t ev[3];
+};
+size_t diag_work_bytes(const DenseShape& sh);
+hipError_t launch_diag_sweep(int dev, const DenseOps& ops, const DenseShape& sh,
+                             const DiagBuffers& bf, const SweepParams& sp, hipStream_t st);
 hipError_t launch_dense_norms(const DenseOps& ops, int d, int dp, int K, const double* u, int nb,
                               int N, double dt, double* theta, hipStream_t st);
 hipError_t launch_dense_sweep(const DenseOps& ops, const DenseShape& sh, const DenseBuffers& bf,
