@@ -172,6 +172,64 @@ def cfg5_leg(hg, ctx, no_c128):
     return out
 
 
+def gate_leg(hg, ctx, args):
+    """The paper's second workload: a full-basis gate on three coupled transmons
+    (8 levels each, d = S = 512), one step as in its benchmark: DIA storage,
+    dense storage on the matrix cores (Taylor products), and diagonalisation."""
+    import numpy as np
+    import torch
+    from workloads import make_config
+    from workloads.configs import _amps
+    pg = make_config("gate3", d_t=8)
+    log(f"[bench] gate3 d={pg.dim} S={pg.n_states} N={pg.n_steps}")
+    probg = hg.Problem(ctx, pg.H0, pg.Hk, pg.omega)
+    ug = torch.tensor(pg.u, dtype=torch.float64, device="cuda")
+    pg0 = torch.tensor(pg.psi0, dtype=torch.complex128, device="cuda")
+    tgg = torch.tensor(pg.targets, dtype=torch.complex128, device="cuda")
+    gate = {"workload": "gate3: three coupled transmons (8 levels each), d = 512, "
+                        "full basis S = 512, simultaneous Hadamards, N = 1, dt = 0.25 ns"}
+    for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
+        rg = run_precision(hg, probg, ug, pg0, tgg, pg, dtype, max(args.steps, 3), args.warmup)
+        gate[dtype] = {"value": 1.0 / (rg["ms_per_step"] * 1e-3), "unit": "evals/s",
+                       "ms_per_step": rg["ms_per_step"], "sum_mu": int(np.sum(rg["sum_mu"]))}
+        log(f"[bench] gate3 {dtype}: {gate[dtype]['value']:.2f} evals/s")
+    # the same gate with the operators stored densely, as the paper's benchmark
+    # stores them: every Taylor term is a 512 x 512 by 512 x 512 complex
+    # contraction on the matrix cores; a batch of evaluations fills the chip
+    Bg = args.gate_batch
+    ugb = np.stack([pg.u] + [_amps(np.random.default_rng(200 + b), pg.n_ctrl, pg.n_steps)
+                             for b in range(1, Bg)])
+    ugb_t = torch.tensor(ugb, dtype=torch.float64, device="cuda")
+    probd = hg.Problem(ctx, pg.H0, pg.Hk, pg.omega, dense=True)
+    dense = {"storage": "dense (MFMA path)", "concurrent_evals": Bg,
+             "flops_note": "8 d^2 S flop per complex contraction; per Taylor term "
+                           "(4 + 2K) contractions over forward, reconstruction, co-state and "
+                           "the auxiliary action (E_k products included)"}
+    for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
+        rd = run_precision(hg, probd, ugb_t, pg0, tgg, pg, dtype, max(args.steps, 3),
+                           args.warmup)
+        flops = float(np.sum(rd["sum_mu"])) * 8.0 * pg.dim ** 2 * pg.n_states * (4 + 2 * pg.n_ctrl)
+        tf = flops / ((rd["ms_forward"] + rd["ms_backward"]) * 1e-3) / 1e12
+        dense[dtype] = {"value": Bg / (rd["ms_per_step"] * 1e-3), "unit": "evals/s",
+                        "ms_per_step": rd["ms_per_step"], "sum_mu": int(np.sum(rd["sum_mu"])),
+                        "sweep_tflops": tf, "mfma_peak_tflops": PEAK_MFMA_TFLOPS[dtype],
+                        "frac": tf / PEAK_MFMA_TFLOPS[dtype]}
+        log(f"[bench] gate3 dense {dtype}: {dense[dtype]['value']:.2f} evals/s, "
+            f"{tf:.1f} TFLOP/s over the sweep ({100 * tf / PEAK_MFMA_TFLOPS[dtype]:.0f}% of MFMA peak)")
+    gate["dense"] = dense
+    # the same gate by diagonalising H_n per step (App. F): Jacobi eigensolver
+    # in FP64, library GEMMs for the basis changes
+    diag = {"method": "diagonalisation (App. F)", "concurrent_evals": Bg}
+    for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
+        rd = run_precision(hg, probd, ugb_t, pg0, tgg, pg, dtype, max(args.steps, 3),
+                           args.warmup, method="diag")
+        diag[dtype] = {"value": Bg / (rd["ms_per_step"] * 1e-3), "unit": "evals/s",
+                       "ms_per_step": rd["ms_per_step"]}
+        log(f"[bench] gate3 diag {dtype}: {diag[dtype]['value']:.2f} evals/s")
+    gate["diag"] = diag
+    return gate
+
+
 def cpu_baseline(p_full, n_sample):
     """The FP64 oracle on the first n_sample steps of the same workload (all
     states), scaled to one full evaluation."""
@@ -225,6 +283,10 @@ def main():
                     help="skip the d = 8192 leg (columns split over several workgroups)")
     ap.add_argument("--no-gate", action="store_true",
                     help="skip the full-basis gate leg (three coupled transmons)")
+    ap.add_argument("--leg", choices=["all", "cfg3", "gate", "cfg5"], default="all",
+                    help="run one leg only (for profiling): cfg3 = the headline sweeps alone, "
+                         "gate = the three-transmon gate legs, cfg5 = the d = 8192 leg; prints "
+                         "that leg's JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for the "
                          "FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -250,6 +312,15 @@ def main():
     import paper_2304_06200_amd as hg
     from workloads import make_config
     from workloads.configs import _amps
+
+    if args.leg == "cfg5":
+        ctx = hg.Context(0)
+        print(json.dumps({"leg": "cfg5", "cfg5": cfg5_leg(hg, ctx, args.no_c128)}), flush=True)
+        return
+    if args.leg == "gate":
+        ctx = hg.Context(0)
+        print(json.dumps({"leg": "gate", "gate": gate_leg(hg, ctx, args)}), flush=True)
+        return
 
     p = make_config("cfg3")
     B = args.batch
@@ -358,6 +429,9 @@ def main():
                    "measured as the high-water mark of the workspace pool (hipMemPoolAttrUsedMemHigh); "
                    "stored_history = checkpoint every step, i.e. every psi_n kept (Table I)")
     line["memory_per_eval_bytes"] = mem
+    if args.leg == "cfg3":
+        print(json.dumps(line), flush=True)
+        return
     if not args.no_cfg5:
         line["cfg5"] = cfg5_leg(hg, ctx, args.no_c128)
     if not args.no_integrated:
@@ -370,56 +444,7 @@ def main():
             "slowdown": ri["ms_per_step"] / main_r["ms_per_step"]}
         log(f"[bench] c64 + C3: {line['with_integrated_infidelity']['value']:.3f} evals/s")
     if not args.no_gate:
-        # the paper's second workload: a full-basis gate on three coupled transmons
-        # (8 levels each, d = S = 512), one step as in its benchmark
-        pg = make_config("gate3", d_t=8)
-        log(f"[bench] gate3 d={pg.dim} S={pg.n_states} N={pg.n_steps}")
-        probg = hg.Problem(ctx, pg.H0, pg.Hk, pg.omega)
-        ug = torch.tensor(pg.u, dtype=torch.float64, device="cuda")
-        pg0 = torch.tensor(pg.psi0, dtype=torch.complex128, device="cuda")
-        tgg = torch.tensor(pg.targets, dtype=torch.complex128, device="cuda")
-        line["gate"] = {"workload": "gate3: three coupled transmons (8 levels each), d = 512, "
-                                    "full basis S = 512, simultaneous Hadamards, N = 1, dt = 0.25 ns"}
-        for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
-            rg = run_precision(hg, probg, ug, pg0, tgg, pg, dtype, max(args.steps, 3), args.warmup)
-            line["gate"][dtype] = {"value": 1.0 / (rg["ms_per_step"] * 1e-3), "unit": "evals/s",
-                                   "ms_per_step": rg["ms_per_step"],
-                                   "sum_mu": int(np.sum(rg["sum_mu"]))}
-            log(f"[bench] gate3 {dtype}: {line['gate'][dtype]['value']:.2f} evals/s")
-        # the same gate with the operators stored densely, as the paper's benchmark
-        # stores them: every Taylor term is a 512 x 512 by 512 x 512 complex
-        # contraction on the matrix cores; a batch of evaluations fills the chip
-        Bg = args.gate_batch
-        ugb = np.stack([pg.u] + [_amps(np.random.default_rng(200 + b), pg.n_ctrl, pg.n_steps)
-                                 for b in range(1, Bg)])
-        ugb_t = torch.tensor(ugb, dtype=torch.float64, device="cuda")
-        probd = hg.Problem(ctx, pg.H0, pg.Hk, pg.omega, dense=True)
-        dense = {"storage": "dense (MFMA path)", "concurrent_evals": Bg,
-                 "flops_note": "8 d^2 S flop per complex contraction; per Taylor term "
-                               "(4 + 2K) contractions over forward, reconstruction, co-state and "
-                               "the auxiliary action (E_k products included)"}
-        for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
-            rd = run_precision(hg, probd, ugb_t, pg0, tgg, pg, dtype, max(args.steps, 3),
-                               args.warmup)
-            flops = float(np.sum(rd["sum_mu"])) * 8.0 * pg.dim ** 2 * pg.n_states * (4 + 2 * pg.n_ctrl)
-            tf = flops / ((rd["ms_forward"] + rd["ms_backward"]) * 1e-3) / 1e12
-            dense[dtype] = {"value": Bg / (rd["ms_per_step"] * 1e-3), "unit": "evals/s",
-                            "ms_per_step": rd["ms_per_step"], "sum_mu": int(np.sum(rd["sum_mu"])),
-                            "sweep_tflops": tf, "mfma_peak_tflops": PEAK_MFMA_TFLOPS[dtype],
-                            "frac": tf / PEAK_MFMA_TFLOPS[dtype]}
-            log(f"[bench] gate3 dense {dtype}: {dense[dtype]['value']:.2f} evals/s, "
-                f"{tf:.1f} TFLOP/s over the sweep ({100 * tf / PEAK_MFMA_TFLOPS[dtype]:.0f}% of MFMA peak)")
-        line["gate"]["dense"] = dense
-        # the same gate by diagonalising H_n per step (App. F): Jacobi eigensolver
-        # in FP64, library GEMMs for the basis changes
-        diag = {"method": "diagonalisation (App. F)", "concurrent_evals": Bg}
-        for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
-            rd = run_precision(hg, probd, ugb_t, pg0, tgg, pg, dtype, max(args.steps, 3),
-                               args.warmup, method="diag")
-            diag[dtype] = {"value": Bg / (rd["ms_per_step"] * 1e-3), "unit": "evals/s",
-                           "ms_per_step": rd["ms_per_step"]}
-            log(f"[bench] gate3 diag {dtype}: {diag[dtype]['value']:.2f} evals/s")
-        line["gate"]["diag"] = diag
+        line["gate"] = gate_leg(hg, ctx, args)
     if not args.no_serving:
         log(f"[bench] serving stream: {args.serve_requests} requests, {args.serve_inflight} slots")
         budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)
