@@ -92,12 +92,13 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"].strip())
 
 
-def serving(hg, ctx, dtype, n_req, inflight, budget, qps, seed=4):
+def serving(hg, ctx, dtype, n_req, inflight, budget, qps, seed=4, plain=False):
     """cfg4 stream: n_req requests of transmon(3) x cavity(d_c) problems, d_c
     log-uniform in [8, 700], N in [200, 2000], S in [1, 8].  First all at once
     (saturated throughput), then Poisson arrivals at a fixed rate `qps` (the
     same for both precisions) with spread backward sweeps (idle compute units
-    shorten each request); latency is submit-to-finish per request."""
+    shorten each request); latency is submit-to-finish per request.  With
+    `plain`, the same arrivals are replayed once more without spread."""
     import numpy as np
     import torch
     from workloads.configs import serving_request, serving_stream
@@ -123,20 +124,44 @@ def serving(hg, ctx, dtype, n_req, inflight, budget, qps, seed=4):
     rate = qps
     rng = np.random.default_rng(seed + 1000)
     gaps = rng.exponential(1.0 / rate, size=n_req)
-    hs = []
-    t0 = time.perf_counter()
-    t_next = t0
-    for i in range(n_req):
-        t_next += gaps[i]
-        delay = t_next - time.perf_counter()
-        if delay > 0:
-            time.sleep(delay)
-        hs.append(sv.submit(*dev[i][:1], *dev[i][1:], reqs[i].dt, spread=True, **kw(reqs[i])))
-    lats = [sv.wait(h)[1] for h in hs]
+
+    def poisson(spread):
+        hs = []
+        t0 = time.perf_counter()
+        t_next = t0
+        for i in range(n_req):
+            t_next += gaps[i]
+            delay = t_next - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            hs.append(sv.submit(*dev[i][:1], *dev[i][1:], reqs[i].dt, spread=spread, **kw(reqs[i])))
+            if (i + 1) % 128 == 0:
+                log(f"  serving {dtype}: {i + 1} of {n_req} submitted")
+        st = hg.percentiles([sv.wait(h)[1] for h in hs])
+        log(f"  serving {dtype}: at {rate:.2f} req/s{' with spread' if spread else ''} "
+            f"p50 {st['p50_ms']:.0f} ms p99 {st['p99_ms']:.0f} ms")
+        return st
+    out = {"saturated_req_per_s": sat, "offered_req_per_s": rate, "spread": True, **poisson(True)}
+    if plain:
+        out["without_spread"] = poisson(False)
     sv.close()
-    st = hg.percentiles(lats)
-    log(f"  serving {dtype}: at {rate:.2f} req/s p50 {st['p50_ms']:.0f} ms p99 {st['p99_ms']:.0f} ms")
-    return {"saturated_req_per_s": sat, "offered_req_per_s": rate, "spread": True, **st}
+    return out
+
+
+def serving_leg(hg, ctx, args):
+    import torch
+    log(f"[bench] serving stream: {args.serve_requests} requests, {args.serve_inflight} slots")
+    budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)
+    out = {
+        "workload": "cfg4: transmon(3) x cavity(d_c log-uniform 8..700), N 200..2000, S 1..8, "
+                    f"dt=1 ns, tau=1e-10, Poisson arrivals at {args.serve_qps:g} req/s",
+        "requests": args.serve_requests, "slots": args.serve_inflight, "hbm_budget_bytes": budget}
+    dtypes = ["c128"] if args.only_c128 else (["c64"] if args.no_c128 else ["c64", "c128"])
+    for dtype in dtypes:
+        out[dtype] = serving(hg, ctx, dtype, args.serve_requests, args.serve_inflight, budget,
+                             args.serve_qps, plain=args.serve_plain)
+    out["p99_ms"] = out[dtypes[0]]["p99_ms"]
+    return out
 
 
 def cfg5_leg(hg, ctx, no_c128):
@@ -283,10 +308,14 @@ def main():
                     help="skip the d = 8192 leg (columns split over several workgroups)")
     ap.add_argument("--no-gate", action="store_true",
                     help="skip the full-basis gate leg (three coupled transmons)")
-    ap.add_argument("--leg", choices=["all", "cfg3", "gate", "cfg5"], default="all",
+    ap.add_argument("--leg", choices=["all", "cfg3", "gate", "cfg5", "serve"], default="all",
                     help="run one leg only (for profiling): cfg3 = the headline sweeps alone, "
-                         "gate = the three-transmon gate legs, cfg5 = the d = 8192 leg; prints "
-                         "that leg's JSON")
+                         "gate = the three-transmon gate legs, cfg5 = the d = 8192 leg, serve = "
+                         "the serving stream; prints that leg's JSON")
+    ap.add_argument("--only-c128", action="store_true",
+                    help="with --leg serve: the complex128 stream only")
+    ap.add_argument("--serve-plain", action="store_true",
+                    help="also replay the Poisson arrivals without spread backward sweeps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (reference for the "
                          "FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -320,6 +349,10 @@ def main():
     if args.leg == "gate":
         ctx = hg.Context(0)
         print(json.dumps({"leg": "gate", "gate": gate_leg(hg, ctx, args)}), flush=True)
+        return
+    if args.leg == "serve":
+        ctx = hg.Context(0)
+        print(json.dumps({"leg": "serve", "served": serving_leg(hg, ctx, args)}), flush=True)
         return
 
     p = make_config("cfg3")
@@ -446,16 +479,7 @@ def main():
     if not args.no_gate:
         line["gate"] = gate_leg(hg, ctx, args)
     if not args.no_serving:
-        log(f"[bench] serving stream: {args.serve_requests} requests, {args.serve_inflight} slots")
-        budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)
-        line["served"] = {
-            "workload": "cfg4: transmon(3) x cavity(d_c log-uniform 8..700), N 200..2000, S 1..8, "
-                        f"dt=1 ns, tau=1e-10, Poisson arrivals at {args.serve_qps:g} req/s",
-            "requests": args.serve_requests, "slots": args.serve_inflight, "hbm_budget_bytes": budget}
-        for dtype in (["c64"] if args.no_c128 else ["c64", "c128"]):
-            line["served"][dtype] = serving(hg, ctx, dtype, args.serve_requests,
-                                            args.serve_inflight, budget, args.serve_qps)
-        line["served"]["p99_ms"] = line["served"]["c64"]["p99_ms"]
+        line["served"] = serving_leg(hg, ctx, args)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {args.cpu_sample} steps")
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_sample)

@@ -182,6 +182,7 @@ bool plan_split(const std::vector<std::vector<std::vector<Entry>>>& ops, int64_t
         return std::llabs((int64_t)o) <= hh ? o : (int)((int64_t)o / L) * c.seg;
       };
       c.ops.W = g.W;
+      c.ops.npure = g.npure;
       c.ops.halo = 0;
       for (int e = 0; e < g.W; ++e) {
         c.ops.off[e] = local(g.off[e]);
@@ -307,12 +308,14 @@ static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, c
   std::vector<std::set<int64_t>> koff(K);
   int64_t sigma = 0, nnz = 0;
   std::vector<int64_t> nnz_ctrl(K, 0);
+  std::set<int64_t> complex_off;  // offsets with a non-zero imaginary part in some operator
   for (int64_t i = 0; i < dim; ++i) {
     std::set<int64_t> cols;
     for (int o = 0; o <= K; ++o)
       for (auto& e : ops[o][i]) {
         cols.insert(e.col);
         uoff.insert(e.col - i);
+        if (e.im != 0.0) complex_off.insert(e.col - i);
         if (o > 0) {
           koff[o - 1].insert(e.col - i);
           nnz_ctrl[o - 1]++;
@@ -349,9 +352,24 @@ static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, c
     *out = p.release();
     return HG_OK;
   }
-  if ((int)uoff.size() > kMaxDiagKernels)
-    return fail(HG_ERR_UNSUPPORTED, "union pattern has " + std::to_string(uoff.size()) +
-                                        " diagonals; the DIA kernels support at most 13 "
+  // Union order: the main diagonal first, then the other diagonals on which
+  // every operator is real (B = -i dt/s H is purely imaginary there, so its
+  // products take half the multiply-adds), then the rest.  A main diagonal
+  // that is absent, or complex somewhere, keeps slot 0 as an all-zero
+  // diagonal and goes to a slot of its own at the end, so slot 0 is always
+  // purely imaginary.
+  const bool diag_slot = !uoff.count(0) || complex_off.count(0);
+  std::vector<int64_t> order{0};
+  for (int64_t o : uoff)
+    if (o != 0 && !complex_off.count(o)) order.push_back(o);
+  const int npure = (int)order.size();
+  for (int64_t o : uoff)
+    if (o != 0 && complex_off.count(o)) order.push_back(o);
+  if (diag_slot && uoff.count(0)) order.push_back(0);
+  if ((int)order.size() > kMaxDiagKernels)
+    return fail(HG_ERR_UNSUPPORTED, "union pattern has " + std::to_string(order.size()) +
+                                        " diagonals (counting a slot for the main diagonal); the "
+                                        "DIA kernels support at most 13 "
                                         "(hg_problem_create_dense stores operators densely)");
   for (int k = 0; k < K; ++k)
     if ((int)koff[k].size() > kMaxDiagCtrl)
@@ -366,13 +384,13 @@ static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, c
   p->nnz = nnz;
   p->nnz_ctrl = nnz_ctrl;
   DevOps& d = p->ops;
-  d.W = (int)uoff.size();
+  d.W = (int)order.size();
+  d.npure = npure;
   std::map<int64_t, int> slot;
-  int e = 0;
-  for (int64_t o : uoff) {
-    d.off[e] = (int)o;
-    slot[o] = e++;
-    d.halo = std::max<int>(d.halo, (int)std::llabs(o));
+  for (int e = 0; e < d.W; ++e) {
+    d.off[e] = (int)order[e];
+    slot[order[e]] = e;  // a complex main diagonal maps to its own (last) slot
+    d.halo = std::max<int>(d.halo, (int)std::llabs(order[e]));
   }
   for (int k = 0; k < K; ++k) {
     d.WK[k] = (int)koff[k].size();
@@ -936,6 +954,7 @@ static hg_status shape_for(const hg_problem* p, const hg_eval_desc* d, SweepShap
       sweep_supported(p->ops, (int)p->dim, K, c128, p->ctx->lds_per_block, sh, &why);
       return fail(HG_ERR_UNSUPPORTED, why);
     }
+    sh->pure = p->ops.npure >= 3 ? 3 : 1;
     sh->spread = 1;
     choose_spread(p, d, sh);
   }

@@ -28,6 +28,7 @@ void set_error(const std::string& msg);
 // holds the entry (i, i + off[e]), zero where that column is outside the matrix.
 struct DevOps {
   int W = 0;                       // number of union diagonals
+  int npure = 0;                   // leading union diagonals on which H_0 and every H_k are real
   int off[kMaxDiag] = {0};
   int WK[kMaxCtrl] = {0};          // diagonals per control
   int offk[kMaxCtrl][kMaxDiagCtrl] = {{0}};
@@ -127,6 +128,7 @@ struct SweepShape {
   bool c128;
   int parts;                             // workgroups per state column (1 = no split)
   int spread;                            // backward workgroups sharing a column's controls
+  int pure;                              // leading diagonals taken as purely imaginary in B (1 or 3)
 };
 hipError_t launch_step_norms(const DevOps& ops, int dim, int K, const double* u, int nb,
                              int N, double dt, double* theta, hipStream_t st);

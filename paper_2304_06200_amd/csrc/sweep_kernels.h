@@ -84,6 +84,25 @@ __device__ __forceinline__ void cmac(cx<R>& acc, const cx<R>& a, const cx<R>& b)
   acc.im = fma(a.im, b.re, acc.im);
 }
 
+// acc += a b for a purely imaginary a (a.re is not read): the two
+// multiply-adds of cmac whose factor a.re is zero are left out, which gives
+// the same result (up to the sign of a zero).
+template <typename R>
+__device__ __forceinline__ void cmac_im(cx<R>& acc, const cx<R>& a, const cx<R>& b) {
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+
+// Coefficient q of a row of B: the first PU union diagonals are those on which
+// every operator is real, where B = -i (dt/s) H is purely imaginary.
+template <int PU, typename R>
+__device__ __forceinline__ void bmac(int q, cx<R>& acc, const cx<R>& a, const cx<R>& b) {
+  if (q < PU)
+    cmac_im(acc, a, b);
+  else
+    cmac(acc, a, b);
+}
+
 // Hide a value from loop-invariant code motion: address arithmetic built on
 // it is redone where it is used instead of being hoisted out of the time loop
 // (which would pin one 64-bit address per operator entry in registers).
@@ -432,7 +451,7 @@ __device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t
 // add of a per-row base (VGPR) and the diagonal's offset (SGPR); keeping all
 // RPT*W addresses in registers instead spills at these register budgets and
 // did not make the forward kernel faster.
-template <typename R, int RPT, int NR, int W, int V, int WK, bool AUX, bool SRC1, int LR = RPT>
+template <typename R, int RPT, int NR, int W, int PU, int V, int WK, bool AUX, bool SRC1, int LR = RPT>
 __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, int g0,
                                             const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                             const cx<R> (&bv)[RPT][W],
@@ -476,7 +495,7 @@ __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, i
       }
       if (q < W) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) cmac(t[v], bv[r][q], ring[c % NS][v / L::VP].v[v % L::VP]);
+        for (int v = 0; v < V; ++v) bmac<PU>(q, t[v], bv[r][q], ring[c % NS][v / L::VP].v[v % L::VP]);
       } else {
         const int v = 1 + (q - W) / WK, qq = (q - W) % WK;
         cmac(t[v], ek[v][r][qq], ring[c % NS][0].v[0]);
@@ -506,7 +525,7 @@ __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, i
 
 // The shared tail slab's share of one Taylor term: vector VT of the last row
 // (RPT-1) only, with the same products as taylor_term for that vector.
-template <typename R, int RPT, int W, int V, int WK, bool AUX, bool SRC1, int VT, int LR>
+template <typename R, int RPT, int W, int PU, int V, int WK, bool AUX, bool SRC1, int VT, int LR>
 __device__ __forceinline__ void tail_piece(uint32_t base, const SweepArgs& a, int g0,
                                            const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                            const cx<R> (&bv)[RPT][W],
@@ -532,7 +551,7 @@ __device__ __forceinline__ void tail_piece(uint32_t base, const SweepArgs& a, in
   }
   C t{(R)0, (R)0};
 #pragma unroll
-  for (int q = 0; q < W; ++q) cmac(t, bv[r][q], x[q]);
+  for (int q = 0; q < W; ++q) bmac<PU>(q, t, bv[r][q], x[q]);
   if constexpr (AUX && VT > 0) {
 #pragma unroll
     for (int q = 0; q < WK; ++q) cmac(t, ek[VT][r][q], y[q]);
@@ -544,7 +563,7 @@ __device__ __forceinline__ void tail_piece(uint32_t base, const SweepArgs& a, in
   if (ok[r]) lds_st(rb + opaque_s(base + DST) + vo, t);
 }
 
-template <typename R, int RPT, int W, int V, int WK, bool AUX, bool SRC1, int LR>
+template <typename R, int RPT, int W, int PU, int V, int WK, bool AUX, bool SRC1, int LR>
 __device__ __forceinline__ void tail_share(int tv, uint32_t base, const SweepArgs& a, int g0,
                                            const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                            const cx<R> (&bv)[RPT][W],
@@ -552,16 +571,16 @@ __device__ __forceinline__ void tail_share(int tv, uint32_t base, const SweepArg
                                            cx<R> (&acc)[RPT][V]) {
   switch (tv) {
     case 0:
-      tail_piece<R, RPT, W, V, WK, AUX, SRC1, 0, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 0, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
       break;
     case 1:
-      if constexpr (V > 1) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 1, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      if constexpr (V > 1) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 1, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
       break;
     case 2:
-      if constexpr (V > 2) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 2, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      if constexpr (V > 2) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 2, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
       break;
     case 3:
-      if constexpr (V > 3) tail_piece<R, RPT, W, V, WK, AUX, SRC1, 3, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      if constexpr (V > 3) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 3, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
       break;
     default:
       break;
@@ -576,7 +595,7 @@ __device__ __forceinline__ void tail_share(int tv, uint32_t base, const SweepArg
 // `base` is the byte offset of buffer 0, plane 0, row 0.  The term loop is
 // unrolled by two so the buffer being read is a compile-time choice.  Ends
 // with a barrier, so the block may be rewritten right away.
-template <typename R, int RPT, int W, int V, int WK, bool AUX, int LR, bool SPLIT>
+template <typename R, int RPT, int W, int PU, int V, int WK, bool AUX, int LR, bool SPLIT>
 __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, int g0,
                                              const uint32_t (&rowb)[RPT],
                                              const bool (&ok)[RPT], const bool (&sv)[RPT],
@@ -600,19 +619,19 @@ __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, 
     for (int j = 1; j <= m; j += 2) {
       const R i1 = sgn * lds_ld<R>(kInvOff + j * (int)sizeof(R));
       if (full)
-        taylor_term<R, RPT, RPT, W, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, i1, acc);
+        taylor_term<R, RPT, RPT, W, PU, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, i1, acc);
       else
-        taylor_term<R, RPT, NRS, W, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, i1, acc);
-      if (share) tail_share<R, RPT, W, V, WK, AUX, false, LR>(tv, base, a, g0, rowb, ok, bv, ek, i1, acc);
+        taylor_term<R, RPT, NRS, W, PU, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, i1, acc);
+      if (share) tail_share<R, RPT, W, PU, V, WK, AUX, false, LR>(tv, base, a, g0, rowb, ok, bv, ek, i1, acc);
       __syncthreads();
       if constexpr (SPLIT) halo_exchange<R, LR, V>(a, base, BL::bs(a.d), xs);
       if (j + 1 <= m) {
         const R i2 = sgn * lds_ld<R>(kInvOff + (j + 1) * (int)sizeof(R));
         if (full)
-          taylor_term<R, RPT, RPT, W, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, i2, acc);
+          taylor_term<R, RPT, RPT, W, PU, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, i2, acc);
         else
-          taylor_term<R, RPT, NRS, W, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, i2, acc);
-        if (share) tail_share<R, RPT, W, V, WK, AUX, true, LR>(tv, base, a, g0, rowb, ok, bv, ek, i2, acc);
+          taylor_term<R, RPT, NRS, W, PU, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, i2, acc);
+        if (share) tail_share<R, RPT, W, PU, V, WK, AUX, true, LR>(tv, base, a, g0, rowb, ok, bv, ek, i2, acc);
         __syncthreads();
         if constexpr (SPLIT) halo_exchange<R, LR, V>(a, base, 0u, xs);
       }
@@ -643,7 +662,7 @@ __device__ __forceinline__ void renormalise(cx<R> (&p)[RPT], double* red, const 
 // TPB threads per workgroup; the LDS layout is that of LR = RPT*TPB/512 rows
 // per 512 threads, so the forward can run 1024 threads (4 waves per SIMD, to
 // hide the latency of its short, barrier-separated terms).
-template <typename R, int RPT, int W, int TPB, bool SPLIT>
+template <typename R, int RPT, int W, int PU, int TPB, bool SPLIT>
 __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
   using C = cx<R>;
   constexpr int LR = RPT * TPB / kMaxThreads;
@@ -695,7 +714,7 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
     const int s = a.ssch[(size_t)b * a.N + n];
     C bv[RPT][W];
     assemble_B<R, RPT, W>(a, vals, ub, n, row, ok, a.dt / (double)s, bv);
-    taylor_block<R, RPT, W, 1, 1, false, LR, SPLIT>(base, a, 0, rowb, ok, sv, kNotShared, bv, ek,
+    taylor_block<R, RPT, W, PU, 1, 1, false, LR, SPLIT>(base, a, 0, rowb, ok, sv, kNotShared, bv, ek,
                                                     m, s, (R)1, acc, xs);
     if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
       C p[RPT];
@@ -766,7 +785,7 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
 // group) so that the (1+G)-vector double-buffered block fits in LDS.
 // TPB threads per workgroup, LDS layout of LR = RPT*TPB/512 rows per 512
 // threads (as in the forward kernel).
-template <typename R, int RPT, int W, int WK, int G, int TPB, bool SPLIT>
+template <typename R, int RPT, int W, int PU, int WK, int G, int TPB, bool SPLIT>
 __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   using C = cx<R>;
   constexpr int V2 = 1 + G;
@@ -916,7 +935,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       C bv[RPT][W];
       assemble_B<R, RPT, W>(a, vals, ub, n, row, ok, a.dt / (double)s, bv);
       C ekf[1][RPT][1];
-      taylor_block<R, RPT, W, 1, 1, false, LR, SPLIT>(basef, a, 0, rowbf, ok, sv, tvp, bv, ekf,
+      taylor_block<R, RPT, W, PU, 1, 1, false, LR, SPLIT>(basef, a, 0, rowbf, ok, sv, tvp, bv, ekf,
                                                       m, s, (R)1, f, xs);
       if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
         C p[RPT];
@@ -940,7 +959,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
 
     if (!ckpt) {
       // phase 1: psi and Lambda through (T_m(-B))^s together
-      taylor_block<R, RPT, W, 2, 1, false, LR, SPLIT>(base1, a, 0, rowb1, ok, sv, tv1, bv, ek1,
+      taylor_block<R, RPT, W, PU, 2, 1, false, LR, SPLIT>(base1, a, 0, rowb1, ok, sv, tv1, bv, ek1,
                                                       m, s, (R)-1, pl, xs);
       if (a.renorm_every > 0 && n % a.renorm_every == 0) {
         C p[RPT];
@@ -962,7 +981,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r) lm[r][0] = pl[r][1];
       C ekf[1][RPT][1];
-      taylor_block<R, RPT, W, 1, 1, false, LR, SPLIT>(basef, a, 0, rowbf, ok, sv, tvl, bv, ekf,
+      taylor_block<R, RPT, W, PU, 1, 1, false, LR, SPLIT>(basef, a, 0, rowbf, ok, sv, tvl, bv, ekf,
                                                       m, s, (R)-1, lm, xs);
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
@@ -990,7 +1009,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
 #pragma unroll
         for (int v = 1; v < V2; ++v) yx[r][v] = C{(R)0, (R)0};
       }
-      taylor_block<R, RPT, W, V2, WK, true, LR, SPLIT>(base2, a, g0, rowb2, ok, sv, tv2, bv, ek,
+      taylor_block<R, RPT, W, PU, V2, WK, true, LR, SPLIT>(base2, a, g0, rowb2, ok, sv, tv2, bv, ek,
                                                        m, s, (R)1, yx, xs);
       double gv[G];
 #pragma unroll

@@ -264,11 +264,13 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
   a.P = 1;
   a.St = sh.n_states;
   hipError_t e;
+  hipEvent_t* ev = bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr;
+  const bool p3 = sh.pure >= 3;
   switch (width_template(ops.W)) {
-    case 3: e = run_width_3(a, sh, st, bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr); break;
-    case 5: e = run_width_5(a, sh, st, bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr); break;
-    case 9: e = run_width_9(a, sh, st, bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr); break;
-    default: e = run_width_13(a, sh, st, bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr); break;
+    case 3: e = p3 ? run_width_3_p3(a, sh, st, ev) : run_width_3_p1(a, sh, st, ev); break;
+    case 5: e = p3 ? run_width_5_p3(a, sh, st, ev) : run_width_5_p1(a, sh, st, ev); break;
+    case 9: e = p3 ? run_width_9_p3(a, sh, st, ev) : run_width_9_p1(a, sh, st, ev); break;
+    default: e = p3 ? run_width_13_p3(a, sh, st, ev) : run_width_13_p1(a, sh, st, ev); break;
   }
   if (e != hipSuccess) return e;
   if (bf.grad && sh.n_ctrl > 0) {

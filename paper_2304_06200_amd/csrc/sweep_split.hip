@@ -14,11 +14,11 @@ namespace hg {
 
 namespace {
 
-template <typename R, int W, int G>
+template <typename R, int W, int PU, int G>
 hipError_t run_split_kernels(const SweepArgs& a0, const SweepShape& sh, hipStream_t st,
                              hipEvent_t* ev) {
-  auto fk = hg_forward<R, 4, W, kMaxThreads, true>;
-  auto bk = hg_backward<R, 4, W, 2, G, kMaxThreads, true>;
+  auto fk = hg_forward<R, 4, W, PU, kMaxThreads, true>;
+  auto bk = hg_backward<R, 4, W, PU, 2, G, kMaxThreads, true>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fk),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_fwd);
   if (e != hipSuccess) return e;
@@ -44,22 +44,23 @@ hipError_t run_split_kernels(const SweepArgs& a0, const SweepShape& sh, hipStrea
   return e;
 }
 
-template <int W>
+template <int W, int PU>
 hipError_t run_split_width(const SweepArgs& a, const SweepShape& sh, hipStream_t st,
                            hipEvent_t* ev) {
-  if (sh.c128) return run_split_kernels<double, W, 1>(a, sh, st, ev);
+  if (sh.c128) return run_split_kernels<double, W, PU, 1>(a, sh, st, ev);
   switch (sh.groups) {
-    case 1: return run_split_kernels<float, W, 1>(a, sh, st, ev);
-    case 2: return run_split_kernels<float, W, 2>(a, sh, st, ev);
-    default: return run_split_kernels<float, W, 3>(a, sh, st, ev);
+    case 1: return run_split_kernels<float, W, PU, 1>(a, sh, st, ev);
+    case 2: return run_split_kernels<float, W, PU, 2>(a, sh, st, ev);
+    default: return run_split_kernels<float, W, PU, 3>(a, sh, st, ev);
   }
 }
 
 }  // namespace
 
 hipError_t run_split(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev) {
-  if (a.W <= 5) return run_split_width<5>(a, sh, st, ev);
-  return run_split_width<9>(a, sh, st, ev);
+  if (a.W <= 5)
+    return sh.pure >= 3 ? run_split_width<5, 3>(a, sh, st, ev) : run_split_width<5, 1>(a, sh, st, ev);
+  return sh.pure >= 3 ? run_split_width<9, 3>(a, sh, st, ev) : run_split_width<9, 1>(a, sh, st, ev);
 }
 
 }  // namespace hg

@@ -8,10 +8,18 @@
 
 namespace hg {
 
-hipError_t run_width_3(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
-hipError_t run_width_5(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
-hipError_t run_width_9(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
-hipError_t run_width_13(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
+// Per union width W, for PU = 1 (only the main diagonal purely imaginary in B)
+// and PU = 3 (it and two more), one translation unit each.
+#define HG_DECLARE_WIDTH(W)                                                                     \
+  hipError_t run_width_##W##_p1(const SweepArgs& a, const SweepShape& sh, hipStream_t st,     \
+                                hipEvent_t* ev);                                               \
+  hipError_t run_width_##W##_p3(const SweepArgs& a, const SweepShape& sh, hipStream_t st,     \
+                                hipEvent_t* ev);
+HG_DECLARE_WIDTH(3)
+HG_DECLARE_WIDTH(5)
+HG_DECLARE_WIDTH(9)
+HG_DECLARE_WIDTH(13)
+#undef HG_DECLARE_WIDTH
 
 hipError_t launch_integrated(const SweepArgs& a, int nb, hipStream_t st);
 
@@ -21,20 +29,20 @@ hipError_t run_split(const SweepArgs& a, const SweepShape& sh, hipStream_t st, h
 // Zero n counters on the stream (a kernel, so that graph capture records no memset).
 hipError_t launch_fill_u32(uint32_t* p, int n, hipStream_t st);
 
-template <typename R, int RPT, int W, int WK, int G>
+template <typename R, int RPT, int W, int PU, int WK, int G>
 hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream_t st,
                              hipEvent_t* ev) {
-  auto fk = hg_forward<R, RPT, W, kMaxThreads, false>;
-  auto bk = hg_backward<R, RPT, W, WK, G, kMaxThreads, false>;
+  auto fk = hg_forward<R, RPT, W, PU, kMaxThreads, false>;
+  auto bk = hg_backward<R, RPT, W, PU, WK, G, kMaxThreads, false>;
   if constexpr (W <= 9 && RPT <= (W <= 5 ? 6 : 4)) {
     if (sh.fwd_threads > kMaxThreads) {
-      if (sh.fwd_rows_per_thread == 1) fk = hg_forward<R, 1, W, kWideThreads, false>;
-      else if (sh.fwd_rows_per_thread == 2) fk = hg_forward<R, 2, W, kWideThreads, false>;
-      else if constexpr (W <= 5) fk = hg_forward<R, 3, W, kWideThreads, false>;
+      if (sh.fwd_rows_per_thread == 1) fk = hg_forward<R, 1, W, PU, kWideThreads, false>;
+      else if (sh.fwd_rows_per_thread == 2) fk = hg_forward<R, 2, W, PU, kWideThreads, false>;
+      else if constexpr (W <= 5) fk = hg_forward<R, 3, W, PU, kWideThreads, false>;
     }
   }
   if constexpr (sizeof(R) == 4 && WK <= 2 && (RPT <= 2 || (RPT == 3 && W <= 5 && G <= 2))) {
-    if (sh.threads > kMaxThreads) bk = hg_backward<R, RPT, W, WK, G, kWideThreads, false>;
+    if (sh.threads > kMaxThreads) bk = hg_backward<R, RPT, W, PU, WK, G, kWideThreads, false>;
   }
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fk),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_fwd);
@@ -58,12 +66,12 @@ hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream
 }
 
 // Dispatch on precision, rows per thread, control width and group size for a
-// fixed union width W.
-template <int W>
+// fixed union width W and count PU of purely imaginary leading diagonals.
+template <int W, int PU>
 hipError_t run_width(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev) {
   int wk = 1;
   for (int k = 0; k < a.K; ++k) wk = a.WK[k] > wk ? a.WK[k] : wk;
-#define HG_RUN(R, RPT, WKT, G) return run_sweep_kernels<R, RPT, W, WKT, G>(a, sh, st, ev)
+#define HG_RUN(R, RPT, WKT, G) return run_sweep_kernels<R, RPT, W, PU, WKT, G>(a, sh, st, ev)
 #define HG_BY_G_C64(RPT, WKT)           \
   switch (sh.groups) {                  \
     case 1: HG_RUN(float, RPT, WKT, 1); \

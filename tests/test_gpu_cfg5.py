@@ -1,0 +1,54 @@
+"""cfg5 at full size: transmon(8) x cavity(1024), d = 8192, K = 4, N = 5000
+steps of dt = 0.2 ns, S = 4, forbidden-level penalty on.  Each state column
+is split over several co-resident workgroups that exchange halo rows after
+every Taylor term.  HG reconstruction and the checkpointed-state variant (a
+state stored every 100 steps), complex128 and complex64, against the
+Taylor-discretised oracle evaluated offline on the oracle planner's schedule
+(tests/golden/make_golden.py cfg5 --discrete: sparse products, every state
+stored, nothing reconstructed).  The drift of the rebuilt psi_0 and the
+measured workspace high-water mark of each variant are printed: HG memory
+does not grow with N, the checkpoint variant holds ceil(N/C) + C states per
+column (Sec. III.C, Table I)."""
+import numpy as np
+import pytest
+
+from gpu_common import assert_parity, context, golden, log, make_problem, run
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = "cfg5_t8c1024_discrete"
+
+
+@pytest.fixture(scope="module")
+def cfg5_case():
+    ref = golden(GOLDEN)
+    if ref is None:
+        pytest.skip(f"tests/golden/{GOLDEN}_oracle.npz not generated")
+    p = make_config("cfg5")
+    assert p.dim == int(ref["dim"]) == 8192 and p.n_steps == int(ref["n_steps"]) == 5000
+    return p, make_problem(p), ref
+
+
+@pytest.mark.parametrize("dtype,mode", [("c128", "reconstruct"), ("c128", "checkpoint"),
+                                        ("c64", "reconstruct"), ("c64", "checkpoint")])
+def test_cfg5_full_size(cfg5_case, dtype, mode):
+    import paper_2304_06200_amd as hg
+    p, prob, ref = cfg5_case
+    sched = np.asarray(ref["schedule"], dtype=np.int64)
+    sum_mu = int(np.sum(sched[0] * sched[1]))
+    C = 100 if mode == "checkpoint" else 0
+    log(f"[case] cfg5 d={p.dim} N={p.n_steps} S={p.n_states} {dtype} {mode}, sum_mu {sum_mu}")
+    ctx = context()
+    hg.mem_pool_peak(ctx, reset=True)
+    r = run(p, dtype, prob=prob, mode=mode, ckpt_every=C)
+    peak = hg.mem_pool_peak(ctx)
+    log(f"  drift {r.drift[0]:.3e}, workspace high-water mark {peak / 2**20:.1f} MiB")
+    assert int(r.sum_mu[0]) == sum_mu
+    assert_parity(r, ref, dtype, label=f"cfg5-{mode}")
+    if mode == "checkpoint":
+        assert r.drift[0] == 0.0
+    elif dtype == "c128":
+        assert r.drift[0] < 1e-9
+    else:
+        assert r.drift[0] < 1e-3

@@ -79,6 +79,59 @@ def test_wide_pattern_above_2048_rows():
     assert_parity(run(p, "c64"), ref, "c64", label=f"cfg3c177")
 
 
+def _banded(d, diag, off_re, off_im, ctrl_imag, N=10, S=2, seed=3):
+    """A band of offsets 0 and +-1: main diagonal `diag`, off-diagonal with
+    real part off_re and imaginary part off_im; controls a + a^dag and, with
+    ctrl_imag, i(a^dag - a)."""
+    rng = np.random.default_rng(seed)
+    a = destroy(d) / np.sqrt(d)
+    sup = sp.diags((off_re + 1j * off_im) * rng.uniform(0.5, 1.5, d - 1), 1)
+    H0 = sp.csr_matrix(sp.diags(diag) + sup + sup.conj().T)
+    H0.eliminate_zeros()
+    Hk = [sp.csr_matrix(a + a.conj().T)]
+    if ctrl_imag:
+        Hk.append(sp.csr_matrix(1j * (a.conj().T - a)))
+    u = rng.uniform(-0.5, 0.5, (len(Hk), N))
+    psi0 = np.zeros((S, d), complex)
+    for h in range(S):
+        psi0[h, h] = 1.0
+    return Problem(f"band{d}", H0, Hk, 0.4, u, psi0, haar_unitary(S, rng).T @ psi0, None,
+                   w_fid=1.0, w_pen=0.0)
+
+
+@pytest.mark.parametrize("case", ["real", "no_main_diagonal", "complex_main_diagonal"])
+def test_union_order_and_imaginary_diagonals(case):
+    """The union puts the main diagonal first and the other diagonals on which
+    every operator is real next; their entries of B are purely imaginary and
+    take half the multiply-adds.  Cases: everything real (all three leading
+    diagonals purely imaginary in B), no main diagonal at all (an all-zero
+    slot stands in for it), and a main diagonal with an imaginary part inside
+    the Hermiticity tolerance (a slot of its own, after the others).  Against
+    the discretised oracle, both precisions."""
+    from gpu_common import oracle_schedule
+    from oracle import taylor
+    d = 70
+    rng = np.random.default_rng(11)
+    diag = rng.uniform(-2.0, 2.0, d)
+    if case == "real":
+        p = _banded(d, diag, 1.0, 0.0, ctrl_imag=False)
+        width = 3
+    elif case == "no_main_diagonal":
+        p = _banded(d, np.zeros(d), 0.6, 0.8, ctrl_imag=True)
+        width = 3
+    else:
+        p = _banded(d, diag + 1e-14j * np.max(np.abs(diag)), 0.6, 0.8, ctrl_imag=True)
+        width = 4
+    prob = make_problem(p)
+    assert prob.info["ell_width"] == width
+    sched = oracle_schedule(p)
+    ref = taylor.hg_discrete(p.H0, p.Hk, p.u, p.dt, p.psi0, p.targets, sched, omega=p.omega,
+                             w_fid=p.w_fid, w_pen=p.w_pen)
+    log(f"[case] union order {case}")
+    for dt in ("c128", "c64"):
+        assert_parity(run(p, dt, prob=prob), ref, dt, label=case)
+
+
 def test_single_step_single_state_no_penalty():
     p = _cavity_problem(10, K=1, N=1, S=1, penalty=False)
     log("[case] N=1 S=1 K=1 no penalty")
