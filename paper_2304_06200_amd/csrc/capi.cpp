@@ -183,6 +183,8 @@ bool plan_split(const std::vector<std::vector<std::vector<Entry>>>& ops, int64_t
       };
       c.ops.W = g.W;
       c.ops.npure = g.npure;
+      c.ops.ereal = g.ereal;
+      for (int k = 0; k < K; ++k) c.ops.ecl[k] = g.ecl[k];
       c.ops.halo = 0;
       for (int e = 0; e < g.W; ++e) {
         c.ops.off[e] = local(g.off[e]);
@@ -386,6 +388,19 @@ static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, c
   DevOps& d = p->ops;
   d.W = (int)order.size();
   d.npure = npure;
+  // control classes: all entries real (E_k = -i (dt/s) H_k purely imaginary)
+  // or all purely imaginary (E_k real)
+  d.ereal = K > 0;
+  for (int k = 0; k < K; ++k) {
+    bool re_only = true, im_only = true;
+    for (int64_t i = 0; i < dim; ++i)
+      for (auto& en : ops[k + 1][i]) {
+        if (en.im != 0.0) re_only = false;
+        if (en.re != 0.0) im_only = false;
+      }
+    d.ecl[k] = re_only ? 0 : 1;
+    if (!re_only && !im_only) d.ereal = false;
+  }
   std::map<int64_t, int> slot;
   for (int e = 0; e < d.W; ++e) {
     d.off[e] = (int)order[e];
@@ -955,6 +970,9 @@ static hg_status shape_for(const hg_problem* p, const hg_eval_desc* d, SweepShap
       return fail(HG_ERR_UNSUPPORTED, why);
     }
     sh->pure = p->ops.npure >= 3 ? 3 : 1;
+    int wk = 1;
+    for (int k = 0; k < K; ++k) wk = std::max(wk, p->ops.WK[k]);
+    sh->ereal = p->ops.ereal && wk <= 2;
     sh->spread = 1;
     choose_spread(p, d, sh);
   }

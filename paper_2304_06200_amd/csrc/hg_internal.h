@@ -29,6 +29,11 @@ void set_error(const std::string& msg);
 struct DevOps {
   int W = 0;                       // number of union diagonals
   int npure = 0;                   // leading union diagonals on which H_0 and every H_k are real
+  // Every control real (ecl 0: E_k = -i (dt/s) e_k) or purely imaginary (ecl 1:
+  // E_k = (dt/s) e_k), e_k real: the backward can then carry X_k rotated to
+  // the frame where its source E_k Y has real coefficients.
+  bool ereal = false;
+  int ecl[kMaxCtrl] = {0};
   int off[kMaxDiag] = {0};
   int WK[kMaxCtrl] = {0};          // diagonals per control
   int offk[kMaxCtrl][kMaxDiagCtrl] = {{0}};
@@ -129,6 +134,7 @@ struct SweepShape {
   int parts;                             // workgroups per state column (1 = no split)
   int spread;                            // backward workgroups sharing a column's controls
   int pure;                              // leading diagonals taken as purely imaginary in B (1 or 3)
+  bool ereal;                            // auxiliary vectors in the frame of real E_k (DevOps::ereal)
 };
 hipError_t launch_step_norms(const DevOps& ops, int dim, int K, const double* u, int nb,
                              int N, double dt, double* theta, hipStream_t st);

@@ -40,6 +40,7 @@ struct SweepArgs {
   int off[kMaxDiag];
   int WK[kMaxCtrl];
   int offk[kMaxCtrl][kMaxDiagCtrl];
+  int ecl[kMaxCtrl];  // control classes of a rotated-frame backward (DevOps::ecl)
   const double2* vals;   // [(K+1)][W][d]
   const double2* valk;   // [K][kMaxDiagCtrl][d]
   const double* omega;   // [d] or nullptr
@@ -94,13 +95,29 @@ __device__ __forceinline__ void cmac_im(cx<R>& acc, const cx<R>& a, const cx<R>&
 }
 
 // Coefficient q of a row of B: the first PU union diagonals are those on which
-// every operator is real, where B = -i (dt/s) H is purely imaginary.
+// every operator is real, where B = -i (dt/s) H is purely imaginary.  The
+// kernels' PU template code carries this count in its low two bits (1 or 3)
+// and, in bit 2, the rotated frame of the auxiliary vectors (emac).
 template <int PU, typename R>
 __device__ __forceinline__ void bmac(int q, cx<R>& acc, const cx<R>& a, const cx<R>& b) {
-  if (q < PU)
+  if (q < (PU & 3))
     cmac_im(acc, a, b);
   else
     cmac(acc, a, b);
+}
+
+// acc += E_k y for the top block of an auxiliary vector.  In the rotated frame
+// (PU bit 2) the block holds X_k / w_k, whose source e_k y has the real factor
+// e_k (load_E): two multiply-adds.  Multiplying by w_k in {1, -i} is exact, so
+// only the overlap with the co-state needs to know the frame.
+template <int PU, typename R>
+__device__ __forceinline__ void emac(cx<R>& acc, const cx<R>& e, const cx<R>& y) {
+  if constexpr ((PU & 4) != 0) {
+    acc.re = fma(e.re, y.re, acc.re);
+    acc.im = fma(e.re, y.im, acc.im);
+  } else {
+    cmac(acc, e, y);
+  }
 }
 
 // Hide a value from loop-invariant code motion: address arithmetic built on
@@ -179,7 +196,9 @@ __device__ __forceinline__ void assemble_B(const SweepArgs& a, const double2* va
 }
 
 // E_k/s = -i (dt/s) H_k on the control's own diagonals (FP64 -> working precision).
-template <typename R, int RPT, int WK>
+// ER (every control real or purely imaginary): the real factor e_k of
+// E_k = w_k e_k instead (w_k = -i for a real H_k, 1 for an imaginary one), in .re.
+template <typename R, int RPT, int WK, bool ER = false>
 __device__ __forceinline__ void load_E(const SweepArgs& a, const double2* valk, int k, bool active,
                                        const int (&row)[RPT], const bool (&ok)[RPT], double cs,
                                        cx<R> (&ek)[RPT][WK]) {
@@ -191,8 +210,12 @@ __device__ __forceinline__ void load_E(const SweepArgs& a, const double2* valk, 
       double er = 0.0, ei = 0.0;
       if (active && q < a.WK[k] && ok[r]) {
         const double2 v = valk[((size_t)k * kMaxDiagCtrl + q) * a.d + i];
-        er = cs * v.y;
-        ei = -cs * v.x;
+        if (ER) {
+          er = cs * (a.ecl[k] ? v.y : v.x);
+        } else {
+          er = cs * v.y;
+          ei = -cs * v.x;
+        }
       }
       ek[r][q] = cx<R>{(R)er, (R)ei};
     }
@@ -498,7 +521,7 @@ __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, i
         for (int v = 0; v < V; ++v) bmac<PU>(q, t[v], bv[r][q], ring[c % NS][v / L::VP].v[v % L::VP]);
       } else {
         const int v = 1 + (q - W) / WK, qq = (q - W) % WK;
-        cmac(t[v], ek[v][r][qq], ring[c % NS][0].v[0]);
+        emac<PU>(t[v], ek[v][r][qq], ring[c % NS][0].v[0]);
       }
       if (q == NIR - 1) {  // row complete
 #pragma unroll
@@ -554,7 +577,7 @@ __device__ __forceinline__ void tail_piece(uint32_t base, const SweepArgs& a, in
   for (int q = 0; q < W; ++q) bmac<PU>(q, t, bv[r][q], x[q]);
   if constexpr (AUX && VT > 0) {
 #pragma unroll
-    for (int q = 0; q < WK; ++q) cmac(t, ek[VT][r][q], y[q]);
+    for (int q = 0; q < WK; ++q) emac<PU>(t, ek[VT][r][q], y[q]);
   }
   t.re *= inv;
   t.im *= inv;
@@ -996,7 +1019,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       C ek[V2][RPT][WK];
 #pragma unroll
       for (int v = 1; v < V2; ++v)
-        load_E<R, RPT, WK>(a, valk, g0 + v - 1, g0 + v - 1 < K, row, ok, cs, ek[v]);
+        load_E<R, RPT, WK, (PU & 4) != 0>(a, valk, g0 + v - 1, g0 + v - 1 < K, row, ok, cs, ek[v]);
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
 #pragma unroll
@@ -1011,6 +1034,12 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       }
       taylor_block<R, RPT, W, PU, V2, WK, true, LR, SPLIT>(base2, a, g0, rowb2, ok, sv, tv2, bv, ek,
                                                        m, s, (R)1, yx, xs);
+      // Re <Lambda_n|X_k>; in the rotated frame X_k = w_k X'_k, so for w_k = -i
+      // Re(-i <Lambda|X'_k>) = Im <Lambda|X'_k>
+      bool rot[G];
+#pragma unroll
+      for (int v = 0; v < G; ++v)
+        rot[v] = (PU & 4) != 0 && g0 + v < K && a.ecl[g0 + v] == 0;
       double gv[G];
 #pragma unroll
       for (int v = 0; v < G; ++v) gv[v] = 0.0;
@@ -1020,7 +1049,8 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
           const C lc = c_cur[opaque(row[r])];
 #pragma unroll
           for (int v = 0; v < G; ++v)
-            gv[v] += (double)lc.re * yx[r][v + 1].re + (double)lc.im * yx[r][v + 1].im;
+            gv[v] += rot[v] ? (double)lc.re * yx[r][v + 1].im - (double)lc.im * yx[r][v + 1].re
+                            : (double)lc.re * yx[r][v + 1].re + (double)lc.im * yx[r][v + 1].im;
         }
       block_sum<G>(gv, red);
       if (tid == 0)

@@ -237,6 +237,7 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
     a.WK[k] = k < sh.n_ctrl ? ops.WK[k] : 0;
     if (k < sh.n_ctrl && ops.WK[k] > wk) wk = ops.WK[k];
     for (int q = 0; q < kMaxDiagCtrl; ++q) a.offk[k][q] = (k < sh.n_ctrl && q < ops.WK[k]) ? ops.offk[k][q] : 0;
+    a.ecl[k] = k < sh.n_ctrl ? ops.ecl[k] : 0;
   }
   a.vals = ops.vals;
   a.valk = ops.valk;
@@ -265,13 +266,21 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
   a.St = sh.n_states;
   hipError_t e;
   hipEvent_t* ev = bf.ev[0] ? const_cast<hipEvent_t*>(bf.ev) : nullptr;
-  const bool p3 = sh.pure >= 3;
-  switch (width_template(ops.W)) {
-    case 3: e = p3 ? run_width_3_p3(a, sh, st, ev) : run_width_3_p1(a, sh, st, ev); break;
-    case 5: e = p3 ? run_width_5_p3(a, sh, st, ev) : run_width_5_p1(a, sh, st, ev); break;
-    case 9: e = p3 ? run_width_9_p3(a, sh, st, ev) : run_width_9_p1(a, sh, st, ev); break;
-    default: e = p3 ? run_width_13_p3(a, sh, st, ev) : run_width_13_p1(a, sh, st, ev); break;
+  const int code = (sh.pure >= 3 ? 1 : 0) + (sh.ereal ? 2 : 0);
+#define HG_BY_CODE(W)                                    \
+  switch (code) {                                        \
+    case 0: e = run_width_##W##_p1(a, sh, st, ev); break;  \
+    case 1: e = run_width_##W##_p3(a, sh, st, ev); break;  \
+    case 2: e = run_width_##W##_p1e(a, sh, st, ev); break; \
+    default: e = run_width_##W##_p3e(a, sh, st, ev); break; \
   }
+  switch (width_template(ops.W)) {
+    case 3: HG_BY_CODE(3) break;
+    case 5: HG_BY_CODE(5) break;
+    case 9: HG_BY_CODE(9) break;
+    default: HG_BY_CODE(13) break;
+  }
+#undef HG_BY_CODE
   if (e != hipSuccess) return e;
   if (bf.grad && sh.n_ctrl > 0) {
     const size_t total = (size_t)sh.n_batch * sh.n_ctrl * sh.n_steps;
@@ -408,6 +417,7 @@ hipError_t launch_split_sweep(const Split& sp, const SweepShape& sh0, const Swee
     a.WK[k] = k < sh.n_ctrl ? ops.WK[k] : 0;
     for (int q = 0; q < kMaxDiagCtrl; ++q)
       a.offk[k][q] = (k < sh.n_ctrl && q < ops.WK[k]) ? ops.offk[k][q] : 0;
+    a.ecl[k] = k < sh.n_ctrl ? ops.ecl[k] : 0;
   }
   a.vals = ops.vals;
   a.valk = ops.valk;

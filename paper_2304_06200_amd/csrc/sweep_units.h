@@ -9,12 +9,17 @@
 namespace hg {
 
 // Per union width W, for PU = 1 (only the main diagonal purely imaginary in B)
-// and PU = 3 (it and two more), one translation unit each.
+// and PU = 3 (it and two more), each with and without the rotated frame of the
+// auxiliary vectors (suffix e): one translation unit each.
 #define HG_DECLARE_WIDTH(W)                                                                     \
   hipError_t run_width_##W##_p1(const SweepArgs& a, const SweepShape& sh, hipStream_t st,     \
                                 hipEvent_t* ev);                                               \
   hipError_t run_width_##W##_p3(const SweepArgs& a, const SweepShape& sh, hipStream_t st,     \
-                                hipEvent_t* ev);
+                                hipEvent_t* ev);                                               \
+  hipError_t run_width_##W##_p1e(const SweepArgs& a, const SweepShape& sh, hipStream_t st,    \
+                                 hipEvent_t* ev);                                              \
+  hipError_t run_width_##W##_p3e(const SweepArgs& a, const SweepShape& sh, hipStream_t st,    \
+                                 hipEvent_t* ev);
 HG_DECLARE_WIDTH(3)
 HG_DECLARE_WIDTH(5)
 HG_DECLARE_WIDTH(9)
@@ -66,11 +71,16 @@ hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream
 }
 
 // Dispatch on precision, rows per thread, control width and group size for a
-// fixed union width W and count PU of purely imaginary leading diagonals.
+// fixed union width W and kernel code PU (count of purely imaginary leading
+// diagonals, plus 4 for the rotated frame of the auxiliary vectors, which is
+// only built for controls of at most 2 diagonals).  complex128 runs at most 6
+// rows per thread in one workgroup (its two-vector block leaves LDS above
+// about 2400 rows; longer columns are split).
 template <int W, int PU>
 hipError_t run_width(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev) {
   int wk = 1;
   for (int k = 0; k < a.K; ++k) wk = a.WK[k] > wk ? a.WK[k] : wk;
+  constexpr bool ER = (PU & 4) != 0;
 #define HG_RUN(R, RPT, WKT, G) return run_sweep_kernels<R, RPT, W, PU, WKT, G>(a, sh, st, ev)
 #define HG_BY_G_C64(RPT, WKT)           \
   switch (sh.groups) {                  \
@@ -80,11 +90,15 @@ hipError_t run_width(const SweepArgs& a, const SweepShape& sh, hipStream_t st, h
   }
 #define HG_BY_WK(RPT)                                   \
   if (sh.c128) {                                        \
-    if (wk <= 2) HG_RUN(double, RPT, 2, 1);             \
-    HG_RUN(double, RPT, 4, 1);                          \
+    if constexpr (RPT <= 6) {                           \
+      if (ER || wk <= 2) HG_RUN(double, RPT, 2, 1);     \
+      if constexpr (!ER) HG_RUN(double, RPT, 4, 1);     \
+    }                                                   \
+    return hipErrorNotSupported;                        \
   }                                                     \
-  if (wk <= 2) { HG_BY_G_C64(RPT, 2) }                  \
-  HG_BY_G_C64(RPT, 4)
+  if (ER || wk <= 2) { HG_BY_G_C64(RPT, 2) }            \
+  if constexpr (!ER) { HG_BY_G_C64(RPT, 4) }            \
+  return hipErrorNotSupported;
   switch (sh.rows_per_thread) {
     case 1: { HG_BY_WK(1) }
     case 2: { HG_BY_WK(2) }

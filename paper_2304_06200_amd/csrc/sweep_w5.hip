@@ -2,8 +2,7 @@
 #include "sweep_units.h"
 
 namespace hg {
-hipError_t run_width_5_p1(const SweepArgs& a, const SweepShape& sh, hipStream_t st,
-                         hipEvent_t* ev) {
+hipError_t run_width_5_p1(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev) {
   return run_width<5, 1>(a, sh, st, ev);
 }
 }  // namespace hg
