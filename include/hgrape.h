@@ -106,7 +106,15 @@ int32_t hg_version(void);
  * Hk is stored on the device by diagonals (DIA: one value per row and union
  * diagonal, zero outside the matrix), each operator's values on it; each Hk
  * also gets its own diagonals for the derivative products.  Duplicate CSR
- * entries are summed, explicit zeros dropped.
+ * entries are summed, explicit zeros dropped.  The main diagonal and the
+ * other diagonals on which every operator is real come first (B is purely
+ * imaginary there; App. D's sparse storage, laid out for the GPU).
+ * Patterns that are not a few diagonals (more than 13 union diagonals, or
+ * more than 4 in a control: e.g. a qubit register's bit flips, offsets
+ * +-2^j) are stored row-indexed instead (ELL: per row up to 13 slots of
+ * column and value, the main diagonal first; per control at most 2 entries
+ * per row), swept by the same kernels with per-row gather columns, one
+ * workgroup per column.
  * A state column is swept by one workgroup holding its term vectors in LDS
  * (Sec. III.C's forward-backward sweep per state).  When a column does not
  * fit one workgroup in some precision (complex128 beyond about 2048 rows,
@@ -116,9 +124,10 @@ int32_t hg_version(void);
  * transmon x cavity basis), are divided by c-range over P co-resident
  * workgroups that exchange their edge rows after every Taylor term.
  * Errors: INVALID_ARG (bad CSR, dim < 1, n_ctrl < 0), NOT_HERMITIAN,
- * NONFINITE, UNSUPPORTED (more than 13 union diagonals, more than 4 diagonals
- * in one control, n_ctrl > 16, dim > 65536, or a column too long for one
- * workgroup in both precisions with no split layout), DEVICE. */
+ * NONFINITE, UNSUPPORTED (a row with more than 13 entries of the union
+ * pattern, or a control with more than 2 entries in a row, when the pattern
+ * needs row-indexed storage; n_ctrl > 16, dim > 65536, or a column too long
+ * for one workgroup in both precisions with no split layout), DEVICE. */
 hg_status hg_problem_create(hg_ctx* ctx, int64_t dim, int32_t n_ctrl,
                             const hg_csr* H0, const hg_csr* Hk,
                             const double* omega_diag, hg_problem** out);
@@ -133,8 +142,10 @@ hg_status hg_problem_create(hg_ctx* ctx, int64_t dim, int32_t n_ctrl,
  * (full-basis gate problems, S = d) and operators that are dense or have
  * more diagonals than the DIA kernels take.  Inputs, validation, sigma' (from
  * the structural pattern), results and precision rules are those of
- * hg_problem_create; only HG_MODE_RECONSTRUCT is built for dense storage
- * (hg_eval returns UNSUPPORTED for the checkpoint mode).  Device memory:
+ * hg_problem_create.  HG_MODE_CHECKPOINT stores whole state blocks every C
+ * steps and re-propagates each segment on the matrix cores (Taylor method
+ * only: with HG_METHOD_DIAG it returns UNSUPPORTED, and HG_METHOD_AUTO then
+ * takes the Taylor method).  Device memory:
  * (n_ctrl+1) dp^2 complex128 here, dp = dim rounded up to 64; per evaluation
  * the embedded operators and the state blocks (hg_eval_footprint).
  * Errors: INVALID_ARG, NOT_HERMITIAN, NONFINITE, UNSUPPORTED (dim > 8192,

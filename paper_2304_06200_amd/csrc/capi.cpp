@@ -218,6 +218,8 @@ hg_problem::~hg_problem() {
   if (ops.vals) (void)hipFree(ops.vals);
   if (ops.valk) (void)hipFree(ops.valk);
   if (ops.omega) (void)hipFree(ops.omega);
+  if (ops.cols) (void)hipFree(ops.cols);
+  if (ops.colk) (void)hipFree(ops.colk);
   if (dops.H) (void)hipFree(dops.H);
   if (split.ops.vals) (void)hipFree(split.ops.vals);
   if (split.ops.valk) (void)hipFree(split.ops.valk);
@@ -275,6 +277,111 @@ hg_status hg_create(int device_ordinal, hg_ctx** out) {
 
 hg_status hg_destroy(hg_ctx* ctx) {
   delete ctx;
+  return HG_OK;
+}
+
+// Row-indexed (ELL) storage for patterns that are not a few diagonals (a
+// qubit register's bit flips, a random sparse coupling): per row the union
+// columns in slots, slot 0 the main diagonal (an all-zero stand-in when the
+// main diagonal is complex somewhere, which then takes an ordinary slot), and
+// per control its own columns (at most 2 per row).  Held by one workgroup per
+// column (no split).
+static hg_status create_ell(hg_ctx* ctx, int64_t dim, int K,
+                            const std::vector<std::vector<std::vector<Entry>>>& ops,
+                            const double* omega_diag, bool diag_complex, int64_t sigma,
+                            int64_t nnz, const std::vector<int64_t>& nnz_ctrl, hg_problem** out) {
+  std::vector<std::vector<int64_t>> rc((size_t)dim);
+  int W = 1;
+  std::vector<int> ek((size_t)std::max(K, 1), 0);
+  for (int64_t i = 0; i < dim; ++i) {
+    std::set<int64_t> cs;
+    for (int o = 0; o <= K; ++o)
+      for (auto& e : ops[o][i]) cs.insert(e.col);
+    std::vector<int64_t>& v = rc[(size_t)i];
+    v.push_back(i);
+    for (int64_t c : cs)
+      if (c != i || diag_complex) v.push_back(c);
+    W = std::max(W, (int)v.size());
+    for (int k = 0; k < K; ++k) ek[k] = std::max(ek[k], (int)ops[k + 1][i].size());
+  }
+  if (W > kMaxDiagKernels)
+    return fail(HG_ERR_UNSUPPORTED, "a row has " + std::to_string(W) + " stored entries (counting a "
+                                    "slot for the main diagonal); the sweep kernels take at most 13 "
+                                    "(hg_problem_create_dense stores operators densely)");
+  for (int k = 0; k < K; ++k)
+    if (ek[k] > 2)
+      return fail(HG_ERR_UNSUPPORTED, "control " + std::to_string(k + 1) + " has " +
+                                          std::to_string(ek[k]) + " entries in a row; row-indexed "
+                                          "storage takes at most 2 (dense storage takes any)");
+  auto p = std::make_unique<hg_problem>();
+  p->ctx = ctx;
+  p->dim = dim;
+  p->n_ctrl = K;
+  p->sigma = (int32_t)std::max<int64_t>(sigma, 1);
+  p->nnz = nnz;
+  p->nnz_ctrl = nnz_ctrl;
+  DevOps& d = p->ops;
+  d.ell = true;
+  d.W = W;
+  d.npure = 1;
+  d.halo = 0;
+  d.ereal = K > 0;
+  for (int k = 0; k < K; ++k) {
+    bool re_only = true, im_only = true;
+    for (int64_t i = 0; i < dim; ++i)
+      for (auto& en : ops[k + 1][i]) {
+        if (en.im != 0.0) re_only = false;
+        if (en.re != 0.0) im_only = false;
+      }
+    d.ecl[k] = re_only ? 0 : 1;
+    if (!re_only && !im_only) d.ereal = false;
+    d.WK[k] = ek[k];
+  }
+  const size_t D = (size_t)dim;
+  std::vector<int32_t> hc((size_t)W * D), hck((size_t)std::max(K, 1) * kMaxDiagCtrl * D);
+  std::vector<double2> hv((size_t)(K + 1) * W * D, double2{0.0, 0.0});
+  std::vector<double2> hk((size_t)std::max(K, 1) * kMaxDiagCtrl * D, double2{0.0, 0.0});
+  for (size_t i = 0; i < D; ++i) {
+    const std::vector<int64_t>& v = rc[i];
+    for (int e = 0; e < W; ++e) hc[(size_t)e * D + i] = (int32_t)(e < (int)v.size() ? v[e] : (int64_t)i);
+    for (int o = 0; o <= K; ++o)
+      for (auto& en : ops[o][i]) {
+        // slot of the column; a complex main diagonal skips the stand-in slot 0
+        int e = (en.col == (int64_t)i && !diag_complex) ? 0 : 1;
+        while (v[e] != en.col) ++e;
+        hv[((size_t)o * W + e) * D + i] = double2{en.re, en.im};
+      }
+    for (int k = 0; k < K; ++k) {
+      int qq = 0;
+      for (auto& en : ops[k + 1][i]) {
+        hck[((size_t)k * kMaxDiagCtrl + qq) * D + i] = (int32_t)en.col;
+        hk[((size_t)k * kMaxDiagCtrl + qq) * D + i] = double2{en.re, en.im};
+        ++qq;
+      }
+      for (; qq < kMaxDiagCtrl; ++qq) hck[((size_t)k * kMaxDiagCtrl + qq) * D + i] = (int32_t)i;
+    }
+  }
+  HG_HIP(hipMalloc(&d.vals, hv.size() * sizeof(double2)));
+  HG_HIP(hipMemcpy(d.vals, hv.data(), hv.size() * sizeof(double2), hipMemcpyHostToDevice));
+  HG_HIP(hipMalloc(&d.valk, hk.size() * sizeof(double2)));
+  HG_HIP(hipMemcpy(d.valk, hk.data(), hk.size() * sizeof(double2), hipMemcpyHostToDevice));
+  HG_HIP(hipMalloc(&d.cols, hc.size() * sizeof(int32_t)));
+  HG_HIP(hipMemcpy(d.cols, hc.data(), hc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HG_HIP(hipMalloc(&d.colk, hck.size() * sizeof(int32_t)));
+  HG_HIP(hipMemcpy(d.colk, hck.data(), hck.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (omega_diag) {
+    HG_HIP(hipMalloc(&d.omega, dim * sizeof(double)));
+    HG_HIP(hipMemcpy(d.omega, omega_diag, dim * sizeof(double), hipMemcpyHostToDevice));
+  }
+  SweepShape sh{};
+  std::string w64, w128;
+  const bool one64 = dim <= (int64_t)kMaxThreads * kMaxRows &&
+                     sweep_supported(d, (int)dim, K, false, ctx->lds_per_block, &sh, &w64);
+  const bool one128 = dim <= (int64_t)kMaxThreads * kMaxRows &&
+                      sweep_supported(d, (int)dim, K, true, ctx->lds_per_block, &sh, &w128);
+  if (!one64 && !one128)
+    return fail(HG_ERR_UNSUPPORTED, "row-indexed storage: " + w64);
+  *out = p.release();
   return HG_OK;
 }
 
@@ -368,15 +475,11 @@ static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, c
   for (int64_t o : uoff)
     if (o != 0 && complex_off.count(o)) order.push_back(o);
   if (diag_slot && uoff.count(0)) order.push_back(0);
-  if ((int)order.size() > kMaxDiagKernels)
-    return fail(HG_ERR_UNSUPPORTED, "union pattern has " + std::to_string(order.size()) +
-                                        " diagonals (counting a slot for the main diagonal); the "
-                                        "DIA kernels support at most 13 "
-                                        "(hg_problem_create_dense stores operators densely)");
-  for (int k = 0; k < K; ++k)
-    if ((int)koff[k].size() > kMaxDiagCtrl)
-      return fail(HG_ERR_UNSUPPORTED, "control " + std::to_string(k + 1) + " has " +
-                                          std::to_string(koff[k].size()) + " diagonals (max 4)");
+  bool wide_ctrl = false;
+  for (int k = 0; k < K; ++k) wide_ctrl = wide_ctrl || (int)koff[k].size() > kMaxDiagCtrl;
+  if ((int)order.size() > kMaxDiagKernels || wide_ctrl)
+    return create_ell(ctx, dim, K, ops, omega_diag, complex_off.count(0) > 0, sigma, nnz, nnz_ctrl,
+                      out);
 
   auto p = std::make_unique<hg_problem>();
   p->ctx = ctx;
@@ -616,8 +719,8 @@ static Workspace layout(const hg_problem* p, int B, int N, int S_true, bool c128
   w.cold = take(dn ? 0 : (size_t)B * S * Q * 3 * d * cs);
   const size_t C = ckpt_every > 0 ? (size_t)std::min(ckpt_every, N) : 0;
   const size_t nseg = ckpt_every > 0 ? ((size_t)N + ckpt_every - 1) / ckpt_every : 0;
-  w.ckpt = take((size_t)B * S * nseg * d * cs);
-  w.segbuf = take((size_t)B * S * Q * C * d * cs);
+  w.ckpt = take(dn ? 0 : (size_t)B * S * nseg * d * cs);
+  w.segbuf = take(dn ? 0 : (size_t)B * S * Q * C * d * cs);
   w.ovl = take((size_t)B * S * 16);
   w.ovt = take(integrated ? (size_t)B * S * N * 16 : 0);
   w.gt = take(integrated ? (size_t)B * N * 16 : 0);
@@ -641,6 +744,10 @@ static Workspace layout(const hg_problem* p, int B, int N, int S_true, bool c128
       w.mat = take((size_t)B * Mp * Mp * rs);
       w.emat = take((size_t)B * K * Mp * Mp * rs);
       w.blocks = take(dense_block_elems(sh) * rs);
+      // checkpoint variant: whole state groups (padded columns, embedded rows)
+      const size_t grp = (size_t)sh.Sp * Mp * rs;
+      w.ckpt = take((size_t)B * nseg * grp);
+      w.segbuf = take((size_t)B * C * grp);
     }
     if (method != HG_METHOD_TAYLOR) w.diag = take(diag_work_bytes(sh));
   }
@@ -672,8 +779,9 @@ static hg_status check_desc(const hg_problem* p, const hg_eval_desc* d) {
                                     "(hg_problem_create_dense)");
   if ((p->n_ctrl > 0 && !d->u) || !d->psi0 || !d->targets)
     return fail(HG_ERR_INVALID_ARG, "NULL device array");
-  if (p->dense && d->mode != HG_MODE_RECONSTRUCT)
-    return fail(HG_ERR_UNSUPPORTED, "dense storage: only the reconstruction mode is built");
+  if (p->dense && d->mode == HG_MODE_CHECKPOINT && d->method == HG_METHOD_DIAG)
+    return fail(HG_ERR_UNSUPPORTED, "the diagonalisation method rebuilds states exactly; the "
+                                    "checkpoint mode is built for the Taylor method");
   return HG_OK;
 }
 
@@ -779,7 +887,7 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
     double mu = 0.0;
     for (int64_t i = 0; i < (int64_t)B * N; ++i) mu += (double)h_m[i] * h_s[i];
     mu /= (double)B * N;
-    use_diag = mu * S >= (c128 ? kAutoDiagC128 : kAutoDiagC64) * ((double)p->dim + S);
+    use_diag = ck == 0 && mu * S >= (c128 ? kAutoDiagC128 : kAutoDiagC64) * ((double)p->dim + S);
   }
 
   SweepBuffers bf{};
@@ -837,6 +945,8 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
     db.blocks = ws + w.blocks;
     db.mat = ws + w.mat;
     db.emat = ws + w.emat;
+    db.ckpt = ck > 0 ? ws + w.ckpt : nullptr;
+    db.segbuf = ck > 0 ? ws + w.segbuf : nullptr;
     db.pen = bf.pen;
     db.ovl = bf.ovl;
     db.ovt = bf.ovt;

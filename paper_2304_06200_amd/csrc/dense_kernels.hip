@@ -656,10 +656,23 @@ hipError_t dense_sweep_t(const DenseOps& ops, const DenseShape& sh, const DenseB
   };
   hipError_t e;
 
+  // Checkpoint variant: the forward stores psi_n every C steps (whole state
+  // groups); the backward re-propagates each segment forward from its
+  // checkpoint, keeping its states, and propagates only Lambda backwards.
+  const int C = sp.ckpt_every;
+  R* ckb = reinterpret_cast<R*>(bf.ckpt);
+  R* segb = reinterpret_cast<R*>(bf.segbuf);
+  const size_t nseg = C > 0 ? (size_t)(N + C - 1) / C : 0;
+  auto save_group = [&](const R* src, size_t src_b, R* dst, size_t dst_b) {
+    hipLaunchKernelGGL(k_dense_copy<R>, dim3(stride_blocks(grp), B), dim3(256), 0, st, src, dst,
+                       src_b, dst_b, grp, (const int32_t*)nullptr, N, 0, 0);
+  };
+
   // ---- forward: psi_n = (T_m(B_n))^s psi_{n-1}, penalty and overlaps ----
   if (bf.ev[0]) (void)hipEventRecord(bf.ev[0], st);
   hipLaunchKernelGGL(k_dense_load<R>, dim3(eg, B), dim3(256), 0, st, psi0, q.P, q.stride, S, Sp,
                      d, dp, 0);
+  if (C > 0) save_group(q.P, q.stride, ckb, nseg * grp);
   for (int n = 0; n < N; ++n) {
     hipLaunchKernelGGL(k_dense_assemble<R>, dim3(asm_blocks, B), dim3(256), 0, st, ops.H,
                        bf.u, ssch, K, N, n, dp, sp.dt, 0, mat, emat, Mp * Mp, (size_t)K * Mp * Mp);
@@ -669,6 +682,8 @@ hipError_t dense_sweep_t(const DenseOps& ops, const DenseShape& sh, const DenseB
     const int rn = sp.renorm_every > 0 && (n + 1) % sp.renorm_every == 0;
     hipLaunchKernelGGL(k_dense_step_end<R>, dim3(S, B), dim3(256), 0, st, q.P, q.stride, dp, d,
                        S, tgt, ops.omega, rn, bf.pen, bf.ovl, bf.ovt, n, N);
+    if (C > 0 && (n + 1) % C == 0 && n + 1 < N)
+      save_group(q.P, q.stride, ckb + (size_t)((n + 1) / C) * grp, nseg * grp);
   }
   hipLaunchKernelGGL(k_dense_finish, dim3(B), dim3(256), 0, st, (const double*)bf.pen,
                      (const double*)bf.ovl, (const double*)bf.ovt, bf.gt, bf.res, S, N, sp.w_fid,
@@ -683,7 +698,30 @@ hipError_t dense_sweep_t(const DenseOps& ops, const DenseShape& sh, const DenseB
   if (bf.ev[1]) (void)hipEventRecord(bf.ev[1], st);
 
   // ---- backward: n = N..1 (index n-1) ----
+  // (checkpoint variant: the Lambda group alone, and a one-group rotation in
+  // the phase-2 buffers for the re-propagation of a segment)
+  const Rot<R> ql{q.P + grp, q.A + grp, {q.T[0] + grp, q.T[1] + grp}, q.stride};
   for (int n = N - 1; n >= 0; --n) {
+    if (C > 0 && (n + 1 == N || (n + 1) % C == 0)) {
+      // entering segment [n0, n]: psi_n0 from its checkpoint, then psi_n0+1..psi_n
+      const int n0 = (n / C) * C;
+      save_group(ckb + (size_t)(n / C) * grp, nseg * grp, wr.P, wr.stride);
+      save_group(wr.P, wr.stride, segb, (size_t)C * grp);
+      for (int k = n0; k < n; ++k) {
+        hipLaunchKernelGGL(k_dense_assemble<R>, dim3(asm_blocks, B), dim3(256), 0, st, ops.H,
+                           bf.u, ssch, K, N, k, dp, sp.dt, 0, mat, emat, Mp * Mp,
+                           (size_t)K * Mp * Mp);
+        if ((e = taylor<R>(sh, wr, 1, 0, (R)1, k, smax(k), mmax(k), mat, emat, msch, ssch, st)) !=
+            hipSuccess)
+          return e;
+        const int rn = sp.renorm_every > 0 && (k + 1) % sp.renorm_every == 0;
+        if (rn)
+          hipLaunchKernelGGL(k_dense_step_end<R>, dim3(S, B), dim3(256), 0, st, wr.P, wr.stride,
+                             dp, d, S, tgt, ops.omega, 1, (double*)nullptr, (double*)nullptr,
+                             (double*)nullptr, k, N);
+        save_group(wr.P, wr.stride, segb + (size_t)(k + 1 - n0) * grp, (size_t)C * grp);
+      }
+    }
     hipLaunchKernelGGL(k_dense_assemble<R>, dim3(asm_blocks, B), dim3(256), 0, st, ops.H,
                        bf.u, ssch, K, N, n, dp, sp.dt, K > 0 ? 1 : 0, mat, emat, Mp * Mp,
                        (size_t)K * Mp * Mp);
@@ -691,11 +729,18 @@ hipError_t dense_sweep_t(const DenseOps& ops, const DenseShape& sh, const DenseB
     hipLaunchKernelGGL(k_dense_copy<R>, dim3(stride_blocks(grp), B), dim3(256), 0, st,
                        (const R*)(q.P + grp), lkeep, q.stride, grp, grp, (const int32_t*)nullptr,
                        N, n, 0);
-    // phase 1: psi_{n-1} and Lambda' through (T_m(-B_n))^s
-    if ((e = taylor<R>(sh, q, 2, 0, (R)-1, n, smax(n), mmax(n), mat, emat, msch, ssch, st)) !=
-        hipSuccess)
+    // phase 1: psi_{n-1} and Lambda' through (T_m(-B_n))^s (checkpoint variant:
+    // Lambda' only, psi_{n-1} from the segment's states)
+    if (C > 0) {
+      if ((e = taylor<R>(sh, ql, 1, 0, (R)-1, n, smax(n), mmax(n), mat, emat, msch, ssch, st)) !=
+          hipSuccess)
+        return e;
+      save_group(segb + (size_t)(n % C) * grp, (size_t)C * grp, q.P, q.stride);
+    } else if ((e = taylor<R>(sh, q, 2, 0, (R)-1, n, smax(n), mmax(n), mat, emat, msch, ssch,
+                              st)) != hipSuccess) {
       return e;
-    if (sp.renorm_every > 0 && n % sp.renorm_every == 0)
+    }
+    if (C == 0 && sp.renorm_every > 0 && n % sp.renorm_every == 0)
       hipLaunchKernelGGL(k_dense_step_end<R>, dim3(S, B), dim3(256), 0, st, q.P, q.stride, dp, d,
                          S, tgt, ops.omega, 1, (double*)nullptr, (double*)nullptr,
                          (double*)nullptr, n, N);

@@ -41,6 +41,13 @@ struct DevOps {
   double2* vals = nullptr;         // [(K+1)][W][dim]: H0 then H_1..H_K on the union pattern
   double2* valk = nullptr;         // [K][kMaxDiagCtrl][dim]: each H_k on its own diagonals
   double* omega = nullptr;         // [dim] or nullptr
+  // Row-indexed (ELL) storage, for patterns that are not a few diagonals:
+  // slot e of row i holds the column cols[e][i] (slot 0 the main diagonal,
+  // or an all-zero stand-in), control k's entry qq the column colk[k][qq][i];
+  // vals/valk are then indexed by slot instead of diagonal, off/offk unused.
+  bool ell = false;
+  int32_t* cols = nullptr;         // [W][dim]
+  int32_t* colk = nullptr;         // [K][kMaxDiagCtrl][dim]
 };
 
 constexpr int kDenseMaxDim = 8192;  // dense storage: (K+1) dp^2 complex128 on the device
@@ -202,6 +209,8 @@ struct DenseBuffers {
   void* blocks;                    // dense_block_elems(shape) working-precision reals
   void* mat;                       // [B][2dp][2dp] embedded A_n/s_n
   void* emat;                      // [B][K][2dp][2dp] embedded E_k/s_n
+  void* ckpt;                      // checkpoint variant: [B][ceil(N/C)] state groups, else null
+  void* segbuf;                    // checkpoint variant: [B][C] state groups, else null
   double* pen;                     // [B][S]
   double* ovl;                     // [B][S][2]
   double* ovt;                     // [B][S][N][2] or null (w_int == 0)

@@ -41,6 +41,8 @@ struct SweepArgs {
   int WK[kMaxCtrl];
   int offk[kMaxCtrl][kMaxDiagCtrl];
   int ecl[kMaxCtrl];  // control classes of a rotated-frame backward (DevOps::ecl)
+  const int32_t* cols;  // row-indexed storage: [W][d] columns of the union slots (DevOps::cols)
+  const int32_t* colk;  // row-indexed storage: [K][kMaxDiagCtrl][d] control columns
   const double2* vals;   // [(K+1)][W][d]
   const double2* valk;   // [K][kMaxDiagCtrl][d]
   const double* omega;   // [d] or nullptr
@@ -193,6 +195,34 @@ __device__ __forceinline__ void assemble_B(const SweepArgs& a, const double2* va
       bv[r][e].im = (R)(-cs * hr);
     }
   }
+}
+
+// Row-indexed storage (kernel code bit 3): the gather column of union slot q
+// for each row of this thread (the row itself where the slot is padding).
+template <int RPT, int W, bool ELL>
+__device__ __forceinline__ void load_cols(const SweepArgs& a, const int (&row)[RPT], int (&cl)[RPT][W]) {
+#pragma unroll
+  for (int r = 0; r < RPT; ++r)
+#pragma unroll
+    for (int q = 0; q < W; ++q)
+      cl[r][q] = (ELL && q < a.W) ? a.cols[(size_t)q * a.d + row[r]] : row[r];
+}
+
+// ... and of control g0 + v - 1's entry qq, for the top blocks v >= 1.
+template <int RPT, int V, int WK, bool ELL>
+__device__ __forceinline__ void load_colk(const SweepArgs& a, int g0, const int (&row)[RPT],
+                                          int (&ck)[V][RPT][WK]) {
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+      for (int q = 0; q < WK; ++q) {
+        const int k = g0 + v - 1;
+        ck[v][r][q] = (ELL && v >= 1 && k < a.K && q < a.WK[k])
+                          ? a.colk[((size_t)k * kMaxDiagCtrl + q) * a.d + row[r]]
+                          : row[r];
+      }
 }
 
 // E_k/s = -i (dt/s) H_k on the control's own diagonals (FP64 -> working precision).
@@ -478,11 +508,13 @@ template <typename R, int RPT, int NR, int W, int PU, int V, int WK, bool AUX, b
 __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, int g0,
                                             const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                             const cx<R> (&bv)[RPT][W],
-                                            const cx<R> (&ek)[V][RPT][WK], R inv,
+                                            const cx<R> (&ek)[V][RPT][WK],
+                                            const int (&cl)[RPT][W], const int (&ckl)[V][RPT][WK], R inv,
                                             cx<R> (&acc)[RPT][V]) {
   using C = cx<R>;
   using L = Blk<R, LR, V>;
   using Row = typename L::Row;
+  constexpr bool ELL = (PU & 8) != 0;  // row-indexed storage: per-row gather columns
   constexpr int NIR = W + (AUX ? (V - 1) * WK : 0);
   constexpr int NI = NR * NIR;  // only the first NR rows (a wave's last slab may be empty)
   constexpr int PD = V == 1 ? (sizeof(R) == 4 ? 6 : 3) : (V == 2 && sizeof(R) == 4 ? 3 : 2);
@@ -499,14 +531,17 @@ __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, i
     if (it < NI) {  // issue the gather of item `it`
       const int r = it / NIR, q = it % NIR;
       if (q < W) {
-        const uint32_t ad = rb[r] + opaque_s((uint32_t)(a.off[q] * L::RB) + base + SRC);
+        const uint32_t ad =
+            ELL ? (uint32_t)opaque(cl[r][q]) * (uint32_t)L::RB + opaque_s(base + SRC)
+                : rb[r] + opaque_s((uint32_t)(a.off[q] * L::RB) + base + SRC);
 #pragma unroll
         for (int p = 0; p < L::NP; ++p) ring[it % NS][p] = lds_ld<Row>(ad + p * L::ps(d));
       } else {
         const int v = 1 + (q - W) / WK, qq = (q - W) % WK;
         const int kk = g0 + v - 1 < a.K ? g0 + v - 1 : 0;
-        ring[it % NS][0].v[0] =
-            lds_ld<C>(rb[r] + opaque_s((uint32_t)(a.offk[kk][qq] * L::RB) + base + SRC));
+        ring[it % NS][0].v[0] = lds_ld<C>(
+            ELL ? (uint32_t)opaque(ckl[v][r][qq]) * (uint32_t)L::RB + opaque_s(base + SRC)
+                : rb[r] + opaque_s((uint32_t)(a.offk[kk][qq] * L::RB) + base + SRC));
       }
     }
     if (it >= PD) {  // consume item `it - PD`
@@ -552,7 +587,8 @@ template <typename R, int RPT, int W, int PU, int V, int WK, bool AUX, bool SRC1
 __device__ __forceinline__ void tail_piece(uint32_t base, const SweepArgs& a, int g0,
                                            const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                            const cx<R> (&bv)[RPT][W],
-                                           const cx<R> (&ek)[V][RPT][WK], R inv,
+                                           const cx<R> (&ek)[V][RPT][WK],
+                                           const int (&cl)[RPT][W], const int (&ckl)[V][RPT][WK], R inv,
                                            cx<R> (&acc)[RPT][V]) {
   using C = cx<R>;
   using L = Blk<R, LR, V>;
@@ -562,15 +598,18 @@ __device__ __forceinline__ void tail_piece(uint32_t base, const SweepArgs& a, in
   const uint32_t vo = (uint32_t)(VT / L::VP) * L::ps(d) + (uint32_t)(VT % L::VP) * L::CS;
   const uint32_t rb = (uint32_t)opaque((int)rowb[r]);
   C x[W];
+  constexpr bool ELL = (PU & 8) != 0;
 #pragma unroll
   for (int q = 0; q < W; ++q)
-    x[q] = lds_ld<C>(rb + opaque_s((uint32_t)(a.off[q] * L::RB) + base + SRC) + vo);
+    x[q] = lds_ld<C>((ELL ? (uint32_t)opaque(cl[r][q]) * (uint32_t)L::RB + opaque_s(base + SRC)
+                          : rb + opaque_s((uint32_t)(a.off[q] * L::RB) + base + SRC)) + vo);
   C y[(AUX && VT > 0) ? WK : 1];
   if constexpr (AUX && VT > 0) {
     const int kk = g0 + VT - 1 < a.K ? g0 + VT - 1 : 0;
 #pragma unroll
     for (int q = 0; q < WK; ++q)
-      y[q] = lds_ld<C>(rb + opaque_s((uint32_t)(a.offk[kk][q] * L::RB) + base + SRC));
+      y[q] = lds_ld<C>(ELL ? (uint32_t)opaque(ckl[VT][r][q]) * (uint32_t)L::RB + opaque_s(base + SRC)
+                           : rb + opaque_s((uint32_t)(a.offk[kk][q] * L::RB) + base + SRC));
   }
   C t{(R)0, (R)0};
 #pragma unroll
@@ -590,20 +629,21 @@ template <typename R, int RPT, int W, int PU, int V, int WK, bool AUX, bool SRC1
 __device__ __forceinline__ void tail_share(int tv, uint32_t base, const SweepArgs& a, int g0,
                                            const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                            const cx<R> (&bv)[RPT][W],
-                                           const cx<R> (&ek)[V][RPT][WK], R inv,
+                                           const cx<R> (&ek)[V][RPT][WK],
+                                           const int (&cl)[RPT][W], const int (&ckl)[V][RPT][WK], R inv,
                                            cx<R> (&acc)[RPT][V]) {
   switch (tv) {
     case 0:
-      tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 0, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 0, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
       break;
     case 1:
-      if constexpr (V > 1) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 1, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      if constexpr (V > 1) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 1, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
       break;
     case 2:
-      if constexpr (V > 2) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 2, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      if constexpr (V > 2) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 2, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
       break;
     case 3:
-      if constexpr (V > 3) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 3, LR>(base, a, g0, rowb, ok, bv, ek, inv, acc);
+      if constexpr (V > 3) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 3, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
       break;
     default:
       break;
@@ -624,7 +664,9 @@ __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, 
                                              const bool (&ok)[RPT], const bool (&sv)[RPT],
                                              int tv,
                                              const cx<R> (&bv)[RPT][W],
-                                             const cx<R> (&ek)[V][RPT][WK], int m, int s, R sgn,
+                                             const cx<R> (&ek)[V][RPT][WK],
+                                             const int (&cl)[RPT][W], const int (&ckl)[V][RPT][WK],
+                                             int m, int s, R sgn,
                                              cx<R> (&acc)[RPT][V], XState& xs) {
   // A wavefront whose last row slab lies past the dimension runs the RPT-1 row
   // variant (wave-uniform choice, both variants fully unrolled).  The waves of
@@ -642,19 +684,19 @@ __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, 
     for (int j = 1; j <= m; j += 2) {
       const R i1 = sgn * lds_ld<R>(kInvOff + j * (int)sizeof(R));
       if (full)
-        taylor_term<R, RPT, RPT, W, PU, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, i1, acc);
+        taylor_term<R, RPT, RPT, W, PU, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i1, acc);
       else
-        taylor_term<R, RPT, NRS, W, PU, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, i1, acc);
-      if (share) tail_share<R, RPT, W, PU, V, WK, AUX, false, LR>(tv, base, a, g0, rowb, ok, bv, ek, i1, acc);
+        taylor_term<R, RPT, NRS, W, PU, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i1, acc);
+      if (share) tail_share<R, RPT, W, PU, V, WK, AUX, false, LR>(tv, base, a, g0, rowb, ok, bv, ek, cl, ckl, i1, acc);
       __syncthreads();
       if constexpr (SPLIT) halo_exchange<R, LR, V>(a, base, BL::bs(a.d), xs);
       if (j + 1 <= m) {
         const R i2 = sgn * lds_ld<R>(kInvOff + (j + 1) * (int)sizeof(R));
         if (full)
-          taylor_term<R, RPT, RPT, W, PU, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, i2, acc);
+          taylor_term<R, RPT, RPT, W, PU, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i2, acc);
         else
-          taylor_term<R, RPT, NRS, W, PU, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, i2, acc);
-        if (share) tail_share<R, RPT, W, PU, V, WK, AUX, true, LR>(tv, base, a, g0, rowb, ok, bv, ek, i2, acc);
+          taylor_term<R, RPT, NRS, W, PU, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i2, acc);
+        if (share) tail_share<R, RPT, W, PU, V, WK, AUX, true, LR>(tv, base, a, g0, rowb, ok, bv, ek, cl, ckl, i2, acc);
         __syncthreads();
         if constexpr (SPLIT) halo_exchange<R, LR, V>(a, base, 0u, xs);
       }
@@ -723,6 +765,9 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
   __syncthreads();
 
   C ek[1][RPT][1];
+  int cl[RPT][W], ckf[1][RPT][1];
+  load_cols<RPT, W, (PU & 8) != 0>(a, row, cl);
+  load_colk<RPT, 1, 1, false>(a, 0, row, ckf);
   double pen = 0.0;
   const double* ub = a.u + (size_t)b * a.K * a.N;
   const int CK = a.ckpt_every;
@@ -738,7 +783,7 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
     C bv[RPT][W];
     assemble_B<R, RPT, W>(a, vals, ub, n, row, ok, a.dt / (double)s, bv);
     taylor_block<R, RPT, W, PU, 1, 1, false, LR, SPLIT>(base, a, 0, rowb, ok, sv, kNotShared, bv, ek,
-                                                    m, s, (R)1, acc, xs);
+                                                    cl, ckf, m, s, (R)1, acc, xs);
     if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
       C p[RPT];
 #pragma unroll
@@ -925,6 +970,10 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   const int tvl = !tailw ? kNotShared : tw == 1 ? 0 : -1;
 
   C ek1[2][RPT][1];
+  int cl[RPT][W], ck1[2][RPT][1], ckf[1][RPT][1];
+  load_cols<RPT, W, (PU & 8) != 0>(a, row, cl);
+  load_colk<RPT, 2, 1, false>(a, 0, row, ck1);
+  load_colk<RPT, 1, 1, false>(a, 0, row, ckf);
   const double* ub = a.u + (size_t)b * K * N;
   // Reconstruction variant: one segment, psi_{n-1} rebuilt by (T_m(-B_n))^s.
   // Checkpoint variant: segments of CK steps swept back last to first; each is
@@ -959,7 +1008,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       assemble_B<R, RPT, W>(a, vals, ub, n, row, ok, a.dt / (double)s, bv);
       C ekf[1][RPT][1];
       taylor_block<R, RPT, W, PU, 1, 1, false, LR, SPLIT>(basef, a, 0, rowbf, ok, sv, tvp, bv, ekf,
-                                                      m, s, (R)1, f, xs);
+                                                      cl, ckf, m, s, (R)1, f, xs);
       if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
         C p[RPT];
 #pragma unroll
@@ -983,7 +1032,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
     if (!ckpt) {
       // phase 1: psi and Lambda through (T_m(-B))^s together
       taylor_block<R, RPT, W, PU, 2, 1, false, LR, SPLIT>(base1, a, 0, rowb1, ok, sv, tv1, bv, ek1,
-                                                      m, s, (R)-1, pl, xs);
+                                                      cl, ck1, m, s, (R)-1, pl, xs);
       if (a.renorm_every > 0 && n % a.renorm_every == 0) {
         C p[RPT];
 #pragma unroll
@@ -1005,7 +1054,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       for (int r = 0; r < RPT; ++r) lm[r][0] = pl[r][1];
       C ekf[1][RPT][1];
       taylor_block<R, RPT, W, PU, 1, 1, false, LR, SPLIT>(basef, a, 0, rowbf, ok, sv, tvl, bv, ekf,
-                                                      m, s, (R)-1, lm, xs);
+                                                      cl, ckf, m, s, (R)-1, lm, xs);
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
         const int i = opaque(row[r]);
@@ -1020,6 +1069,8 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
 #pragma unroll
       for (int v = 1; v < V2; ++v)
         load_E<R, RPT, WK, (PU & 4) != 0>(a, valk, g0 + v - 1, g0 + v - 1 < K, row, ok, cs, ek[v]);
+      int ckl[V2][RPT][WK];
+      load_colk<RPT, V2, WK, (PU & 8) != 0>(a, g0, row, ckl);
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
 #pragma unroll
@@ -1033,7 +1084,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
         for (int v = 1; v < V2; ++v) yx[r][v] = C{(R)0, (R)0};
       }
       taylor_block<R, RPT, W, PU, V2, WK, true, LR, SPLIT>(base2, a, g0, rowb2, ok, sv, tv2, bv, ek,
-                                                       m, s, (R)1, yx, xs);
+                                                       cl, ckl, m, s, (R)1, yx, xs);
       // Re <Lambda_n|X_k>; in the rotated frame X_k = w_k X'_k, so for w_k = -i
       // Re(-i <Lambda|X'_k>) = Im <Lambda|X'_k>
       bool rot[G];

@@ -174,7 +174,8 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
   int wk = 1;
   for (int k = 0; k < K; ++k) wk = std::max(wk, ops.WK[k]);
   int frpt = rpt, fthreads = threads, flr = rpt, blr = rpt;
-  const bool wide = dim > kMaxThreads && ((dim <= 2 * kWideThreads && ops.W <= 9) ||
+  // (not for row-indexed storage, whose gather columns take registers)
+  const bool wide = !ops.ell && dim > kMaxThreads && ((dim <= 2 * kWideThreads && ops.W <= 9) ||
                                           (dim <= 3 * kWideThreads && ops.W <= 5));
   if (wide) {
     frpt = (dim + kWideThreads - 1) / kWideThreads;
@@ -241,6 +242,8 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
   }
   a.vals = ops.vals;
   a.valk = ops.valk;
+  a.cols = ops.ell ? ops.cols : nullptr;
+  a.colk = ops.ell ? ops.colk : nullptr;
   a.omega = ops.omega;
   a.u = bf.u;
   a.msch = bf.m_sched;
@@ -274,11 +277,15 @@ hipError_t launch_sweep(const DevOps& ops, const SweepShape& sh, const SweepBuff
     case 2: e = run_width_##W##_p1e(a, sh, st, ev); break; \
     default: e = run_width_##W##_p3e(a, sh, st, ev); break; \
   }
-  switch (width_template(ops.W)) {
-    case 3: HG_BY_CODE(3) break;
-    case 5: HG_BY_CODE(5) break;
-    case 9: HG_BY_CODE(9) break;
-    default: HG_BY_CODE(13) break;
+  if (ops.ell) {  // row-indexed storage: slot widths 9 and 13
+    e = ops.W <= 9 ? run_width_ell_9(a, sh, st, ev) : run_width_ell_13(a, sh, st, ev);
+  } else {
+    switch (width_template(ops.W)) {
+      case 3: HG_BY_CODE(3) break;
+      case 5: HG_BY_CODE(5) break;
+      case 9: HG_BY_CODE(9) break;
+      default: HG_BY_CODE(13) break;
+    }
   }
 #undef HG_BY_CODE
   if (e != hipSuccess) return e;
@@ -421,6 +428,8 @@ hipError_t launch_split_sweep(const Split& sp, const SweepShape& sh0, const Swee
   }
   a.vals = ops.vals;
   a.valk = ops.valk;
+  a.cols = ops.ell ? ops.cols : nullptr;
+  a.colk = ops.ell ? ops.colk : nullptr;
   a.omega = ops.omega;
   a.u = bf.u;
   a.msch = bf.m_sched;

@@ -25,6 +25,10 @@ HG_DECLARE_WIDTH(5)
 HG_DECLARE_WIDTH(9)
 HG_DECLARE_WIDTH(13)
 #undef HG_DECLARE_WIDTH
+// Row-indexed storage (code bit 3), slot widths 9 and 13, with and without
+// the rotated auxiliary frame.
+hipError_t run_width_ell_9(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
+hipError_t run_width_ell_13(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev);
 
 hipError_t launch_integrated(const SweepArgs& a, int nb, hipStream_t st);
 
@@ -72,15 +76,16 @@ hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream
 
 // Dispatch on precision, rows per thread, control width and group size for a
 // fixed union width W and kernel code PU (count of purely imaginary leading
-// diagonals, plus 4 for the rotated frame of the auxiliary vectors, which is
-// only built for controls of at most 2 diagonals).  complex128 runs at most 6
+// diagonals, plus 4 for the rotated frame of the auxiliary vectors, plus 8 for
+// row-indexed storage; both are only built for controls of at most 2 entries
+// per row).  complex128 runs at most 6
 // rows per thread in one workgroup (its two-vector block leaves LDS above
 // about 2400 rows; longer columns are split).
 template <int W, int PU>
 hipError_t run_width(const SweepArgs& a, const SweepShape& sh, hipStream_t st, hipEvent_t* ev) {
   int wk = 1;
   for (int k = 0; k < a.K; ++k) wk = a.WK[k] > wk ? a.WK[k] : wk;
-  constexpr bool ER = (PU & 4) != 0;
+  constexpr bool ER = (PU & 12) != 0;  // only controls of at most 2 entries per row
 #define HG_RUN(R, RPT, WKT, G) return run_sweep_kernels<R, RPT, W, PU, WKT, G>(a, sh, st, ev)
 #define HG_BY_G_C64(RPT, WKT)           \
   switch (sh.groups) {                  \

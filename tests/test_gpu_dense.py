@@ -128,12 +128,34 @@ def test_dense_batch_is_bitwise_per_evaluation():
         assert_parity(rb, ref, dtype, b=1, label="dense-batch")
 
 
-def test_dense_rejects_checkpoint_mode():
+@pytest.mark.parametrize("C", [1, 3, 7, 50])
+def test_dense_checkpoint_mode(C):
+    """Checkpointed-state variant on dense storage: psi stored every C steps,
+    each segment re-propagated forward from its checkpoint, only Lambda
+    propagated backwards.  Against the exact oracle (penalty and C3 on,
+    segments that do not divide N), and against the reconstruction mode of the
+    same library; the drift of a never-rebuilt psi_0 is its rounding only.  A
+    batch whose evaluations take different (m, s) checks the per-evaluation
+    schedule in the re-propagation."""
+    p = _random_dense(9, 70, 3, 2, 11)
+    U = np.stack([p.u, 1.7 * p.u])
+    ref = _oracle(p, w_int=0.4)
+    for dtype in ("c128", "c64"):
+        log(f"[case] dense checkpoint C={C} {dtype}")
+        a = _run(p, dtype, batch_u=U, w_int=0.4, mode="checkpoint", ckpt_every=C)
+        assert_parity(a, ref, dtype, label=f"dense-ckpt{C}")
+        assert_parity(a, _oracle(p, w_int=0.4, u=U[1]), dtype, b=1, label=f"dense-ckpt{C}-b1")
+        r = _run(p, dtype, batch_u=U, w_int=0.4)
+        assert int(a.sum_mu[0]) == int(r.sum_mu[0]) and int(a.sum_mu[1]) == int(r.sum_mu[1])
+        assert a.drift[0] <= (1e-15 if dtype == "c128" else 1e-6)
+
+
+def test_dense_checkpoint_rejected_with_diagonalisation():
     import paper_2304_06200_amd as hg
     from paper_2304_06200_amd import _lib as L
     p = _random_dense(9, 20, 2, 1, 4)
     with pytest.raises(hg._lib.HGError) as e:
-        _run(p, "c128", mode="checkpoint", ckpt_every=2)
+        _run(p, "c128", mode="checkpoint", ckpt_every=2, method="diag")
     assert e.value.status == L.HG_ERR_UNSUPPORTED
 
 
