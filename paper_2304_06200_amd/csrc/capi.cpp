@@ -280,6 +280,25 @@ hg_status hg_destroy(hg_ctx* ctx) {
   return HG_OK;
 }
 
+// Control classes: every entry of H_k real (ecl 0: E_k = -i (dt/s) H_k purely
+// imaginary) or every entry purely imaginary (ecl 1: E_k real); ereal when
+// all controls are one or the other (the rotated frame of the auxiliary
+// vectors then applies).
+static void classify_controls(const std::vector<std::vector<std::vector<Entry>>>& ops, int64_t dim,
+                              int K, DevOps* d) {
+  d->ereal = K > 0;
+  for (int k = 0; k < K; ++k) {
+    bool re_only = true, im_only = true;
+    for (int64_t i = 0; i < dim; ++i)
+      for (auto& en : ops[k + 1][i]) {
+        if (en.im != 0.0) re_only = false;
+        if (en.re != 0.0) im_only = false;
+      }
+    d->ecl[k] = re_only ? 0 : 1;
+    if (!re_only && !im_only) d->ereal = false;
+  }
+}
+
 // Row-indexed (ELL) storage for patterns that are not a few diagonals (a
 // qubit register's bit flips, a random sparse coupling): per row the union
 // columns in slots, slot 0 the main diagonal (an all-zero stand-in when the
@@ -325,18 +344,8 @@ static hg_status create_ell(hg_ctx* ctx, int64_t dim, int K,
   d.W = W;
   d.npure = 1;
   d.halo = 0;
-  d.ereal = K > 0;
-  for (int k = 0; k < K; ++k) {
-    bool re_only = true, im_only = true;
-    for (int64_t i = 0; i < dim; ++i)
-      for (auto& en : ops[k + 1][i]) {
-        if (en.im != 0.0) re_only = false;
-        if (en.re != 0.0) im_only = false;
-      }
-    d.ecl[k] = re_only ? 0 : 1;
-    if (!re_only && !im_only) d.ereal = false;
-    d.WK[k] = ek[k];
-  }
+  classify_controls(ops, dim, K, &d);
+  for (int k = 0; k < K; ++k) d.WK[k] = ek[k];
   const size_t D = (size_t)dim;
   std::vector<int32_t> hc((size_t)W * D), hck((size_t)std::max(K, 1) * kMaxDiagCtrl * D);
   std::vector<double2> hv((size_t)(K + 1) * W * D, double2{0.0, 0.0});
@@ -491,19 +500,7 @@ static hg_status problem_create_impl(hg_ctx* ctx, int64_t dim, int32_t n_ctrl, c
   DevOps& d = p->ops;
   d.W = (int)order.size();
   d.npure = npure;
-  // control classes: all entries real (E_k = -i (dt/s) H_k purely imaginary)
-  // or all purely imaginary (E_k real)
-  d.ereal = K > 0;
-  for (int k = 0; k < K; ++k) {
-    bool re_only = true, im_only = true;
-    for (int64_t i = 0; i < dim; ++i)
-      for (auto& en : ops[k + 1][i]) {
-        if (en.im != 0.0) re_only = false;
-        if (en.re != 0.0) im_only = false;
-      }
-    d.ecl[k] = re_only ? 0 : 1;
-    if (!re_only && !im_only) d.ereal = false;
-  }
+  classify_controls(ops, dim, K, &d);
   std::map<int64_t, int> slot;
   for (int e = 0; e < d.W; ++e) {
     d.off[e] = (int)order[e];
