@@ -181,7 +181,9 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
     frpt = (dim + kWideThreads - 1) / kWideThreads;
     fthreads = frpt == 1 ? ((dim + 63) / 64) * 64 : kWideThreads;
     flr = frpt * kWideThreads / kMaxThreads;
-    if (!c128 && wk <= 2) {
+    // the backward too: complex64 with controls of at most 2 diagonals, and
+    // complex128 at one row per thread (up to 1024 rows)
+    if (wk <= 2 && (!c128 || frpt == 1)) {
       rpt = frpt;
       threads = fthreads;
       blr = flr;

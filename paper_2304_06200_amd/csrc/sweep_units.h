@@ -50,7 +50,8 @@ hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream
       else if constexpr (W <= 5) fk = hg_forward<R, 3, W, PU, kWideThreads, false>;
     }
   }
-  if constexpr (sizeof(R) == 4 && WK <= 2 && (RPT <= 2 || (RPT == 3 && W <= 5 && G <= 2))) {
+  if constexpr (WK <= 2 && ((sizeof(R) == 4 && (RPT <= 2 || (RPT == 3 && W <= 5 && G <= 2))) ||
+                             (sizeof(R) == 8 && RPT == 1))) {
     if (sh.threads > kMaxThreads) bk = hg_backward<R, RPT, W, PU, WK, G, kWideThreads, false>;
   }
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fk),
