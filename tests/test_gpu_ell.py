@@ -93,6 +93,28 @@ def test_random_sparse_pattern():
                       label="sparse-ckpt")
 
 
+def test_complex_main_diagonal_and_integrated_cost():
+    """Row-indexed storage with a main diagonal that is complex somewhere (an
+    imaginary part inside the Hermiticity tolerance: slot 0 stays an all-zero
+    stand-in, the diagonal takes a slot of its own) and the time-integrated
+    infidelity on, against the Taylor-discretised oracle."""
+    from gpu_common import oracle_schedule
+    from oracle import taylor
+    p = _random_sparse(d=200, N=5, S=2, seed=8)
+    H0 = p.H0.tolil()
+    for i in range(0, p.dim, 7):
+        H0[i, i] = H0[i, i] + 1e-14j
+    p = Problem("sparse-cdiag", sp.csr_matrix(H0), p.Hk, p.dt, p.u, p.psi0, p.targets, p.omega,
+                w_fid=p.w_fid, w_pen=p.w_pen)
+    prob = make_problem(p)
+    sched = oracle_schedule(p)
+    ref = taylor.hg_discrete(p.H0, p.Hk, p.u, p.dt, p.psi0, p.targets, sched, omega=p.omega,
+                             w_fid=p.w_fid, w_pen=p.w_pen, w_int=0.7)
+    for dtype in ("c128", "c64"):
+        log(f"[case] row-indexed, complex main diagonal, C3 on, {dtype}")
+        assert_parity(run(p, dtype, prob=prob, w_int=0.7), ref, dtype, label="sparse-cdiag")
+
+
 def test_batch_and_spread():
     import paper_2304_06200_amd as hg
     p = _qubits(8, 6, S=2)
