@@ -39,6 +39,17 @@ def _sources():
     return out
 
 
+def _cost_rank(src):
+    # the widest sweep instantiations take minutes each: start them first so
+    # the parallel build does not end on one of them
+    f = os.path.basename(src)
+    for rank, prefix in enumerate(("sweep_w13", "sweep_w9", "sweep_ell13", "sweep_ell9",
+                                   "sweep_split", "sweep_w5")):
+        if f.startswith(prefix):
+            return rank
+    return 99
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if os.path.basename(src) == "plan.cpp":
@@ -58,7 +69,7 @@ def build(jobs: int = 0, verbose: bool = False) -> str:
     srcs = _sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(_compile, sorted(srcs, key=_cost_rank)))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + \
         ["-L" + os.path.join(ROCM, "lib"), "-lrocblas", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
