@@ -1077,6 +1077,14 @@ static hg_status shape_for(const hg_problem* p, const hg_eval_desc* d, SweepShap
       return fail(HG_ERR_UNSUPPORTED, why);
     }
     sh->pure = p->ops.npure >= 3 ? 3 : 1;
+    // two state columns per forward workgroup when the launch still has a
+    // workgroup for every compute unit
+    sh->fwd_cpw = 1;
+    if (sh->parts == 1 && sh->lds_fwd2 > 0 && sh->lds_fwd2 <= p->ctx->lds_per_block && S % 2 == 0 &&
+        (int64_t)B * S / 2 >= (int64_t)p->ctx->num_cu) {
+      sh->fwd_cpw = 2;
+      sh->lds_fwd = sh->lds_fwd2;
+    }
     int wk = 1;
     for (int k = 0; k < K; ++k) wk = std::max(wk, p->ops.WK[k]);
     sh->ereal = p->ops.ereal && wk <= 2;

@@ -136,6 +136,8 @@ struct SweepShape {
   int dim, n_ctrl, n_steps, n_states, n_batch;
   int rows_per_thread, threads, groups;  // backward launch; groups = controls per backward pass
   int fwd_rows_per_thread, fwd_threads;  // the forward kernel's own launch shape
+  int fwd_cpw;                           // state columns per forward workgroup (1 or 2)
+  size_t lds_fwd2;                       // forward LDS with two columns (0: not offered)
   size_t lds_fwd, lds_bwd;
   bool c128;
   int parts;                             // workgroups per state column (1 = no split)

@@ -148,6 +148,7 @@ __device__ __forceinline__ void slab_valid(int d, bool (&sv)[RPT]) {
 // Deterministic FP64 block sum of NV values; every thread receives the totals.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
+  static_assert(NV * 16 * 8 <= 512, "the reduction scratch ends where the 1/j table starts");
 #pragma unroll
   for (int i = 0; i < NV; ++i)
 #pragma unroll
@@ -727,15 +728,21 @@ __device__ __forceinline__ void renormalise(cx<R> (&p)[RPT], double* red, const 
 // TPB threads per workgroup; the LDS layout is that of LR = RPT*TPB/512 rows
 // per 512 threads, so the forward can run 1024 threads (4 waves per SIMD, to
 // hide the latency of its short, barrier-separated terms).
-template <typename R, int RPT, int W, int PU, int TPB, bool SPLIT>
+template <typename R, int RPT, int W, int PU, int TPB, bool SPLIT, int CPW = 1>
 __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
+  // CPW state columns of one evaluation per workgroup (CPW = 2: the columns
+  // share B_n, the gather addresses and each term's barrier, and read their
+  // operands pairwise; used when the launch still fills the chip)
+  static_assert(CPW == 1 || !SPLIT, "split columns run one column per workgroup");
   using C = cx<R>;
   constexpr int LR = RPT * TPB / kMaxThreads;
-  using L = Blk<R, LR, 1>;
+  using L = Blk<R, LR, CPW>;
   double* red = reinterpret_cast<double*>(hg_smem);
   const int d = a.d, tid = threadIdx.x, NT = blockDim.x;
-  const int h = blockIdx.x, b = blockIdx.y;
-  const size_t col0 = ((size_t)b * a.S + h) * d;
+  const int h = blockIdx.x * CPW, b = blockIdx.y;
+  size_t col0[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) col0[c] = ((size_t)b * a.S + h + c) * d;
   // a split column's part: its slice of the local operators
   const int part = SPLIT ? h % a.P : 0;
   const double2* vals = a.vals + (SPLIT ? (size_t)part * a.psv : 0);
@@ -752,92 +759,137 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
   uint32_t rowb[RPT];
   bool ok[RPT], sv[RPT];
   slab_valid<RPT>(d, sv);
-  C acc[RPT][1];
+  C acc[RPT][CPW];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int i = tid + r * NT;
     ok[r] = i < d;
     row[r] = ok[r] ? i : d - 1;
     rowb[r] = (uint32_t)row[r] * L::RB;
-    const double2 p = a.psi0[col0 + row[r]];
-    acc[r][0] = ok[r] ? C{(R)p.x, (R)p.y} : C{(R)0, (R)0};
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const double2 p = a.psi0[col0[c] + row[r]];
+      acc[r][c] = ok[r] ? C{(R)p.x, (R)p.y} : C{(R)0, (R)0};
+    }
   }
   __syncthreads();
 
-  C ek[1][RPT][1];
-  int cl[RPT][W], ckf[1][RPT][1];
+  C ek[CPW][RPT][1];
+  int cl[RPT][W], ckf[CPW][RPT][1];
   load_cols<RPT, W, (PU & 8) != 0>(a, row, cl);
-  load_colk<RPT, 1, 1, false>(a, 0, row, ckf);
-  double pen = 0.0;
+  load_colk<RPT, CPW, 1, false>(a, 0, row, ckf);
+  double pen[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) pen[c] = 0.0;
   const double* ub = a.u + (size_t)b * a.K * a.N;
   const int CK = a.ckpt_every;
-  C* ck = CK > 0 ? reinterpret_cast<C*>(a.ckpt) + ((size_t)b * a.S + h) * (size_t)((a.N + CK - 1) / CK) * d
-                 : nullptr;
-  if (ck)
+  C* ck[CPW];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r)
-      if (ok[r]) ck[row[r]] = acc[r][0];
+  for (int c = 0; c < CPW; ++c) {
+    ck[c] = CK > 0 ? reinterpret_cast<C*>(a.ckpt) +
+                         ((size_t)b * a.S + h + c) * (size_t)((a.N + CK - 1) / CK) * d
+                   : nullptr;
+    if (ck[c])
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (ok[r]) ck[c][row[r]] = acc[r][c];
+  }
   for (int n = 0; n < a.N; ++n) {
     const int m = a.msch[(size_t)b * a.N + n];
     const int s = a.ssch[(size_t)b * a.N + n];
     C bv[RPT][W];
     assemble_B<R, RPT, W>(a, vals, ub, n, row, ok, a.dt / (double)s, bv);
-    taylor_block<R, RPT, W, PU, 1, 1, false, LR, SPLIT>(base, a, 0, rowb, ok, sv, kNotShared, bv, ek,
-                                                    cl, ckf, m, s, (R)1, acc, xs);
+    taylor_block<R, RPT, W, PU, CPW, 1, false, LR, SPLIT>(base, a, 0, rowb, ok, sv, kNotShared, bv,
+                                                      ek, cl, ckf, m, s, (R)1, acc, xs);
     if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
-      C p[RPT];
+      if constexpr (CPW == 1) {
+        C p[RPT];
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) p[r] = acc[r][0];
-      renormalise<R, RPT, SPLIT>(p, red, a, xs);
+        for (int r = 0; r < RPT; ++r) p[r] = acc[r][0];
+        renormalise<R, RPT, SPLIT>(p, red, a, xs);
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) acc[r][0] = p[r];
+        for (int r = 0; r < RPT; ++r) acc[r][0] = p[r];
+      } else {
+        double nv[CPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          nv[c] = 0.0;
+#pragma unroll
+          for (int r = 0; r < RPT; ++r)
+            nv[c] += (double)acc[r][c].re * acc[r][c].re + (double)acc[r][c].im * acc[r][c].im;
+        }
+        block_sum<CPW>(nv, red);
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          const R sc = (R)(1.0 / sqrt(nv[c]));
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) {
+            acc[r][c].re *= sc;
+            acc[r][c].im *= sc;
+          }
+        }
+      }
     }
     if (omega) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
         if (ok[r])
-          pen += omega[row[r]] *
-                 ((double)acc[r][0].re * acc[r][0].re + (double)acc[r][0].im * acc[r][0].im);
+#pragma unroll
+          for (int c = 0; c < CPW; ++c)
+            pen[c] += omega[row[r]] *
+                      ((double)acc[r][c].re * acc[r][c].re + (double)acc[r][c].im * acc[r][c].im);
     }
-    if (ck && (n + 1) % CK == 0 && n + 1 < a.N)
+    if (CK > 0 && (n + 1) % CK == 0 && n + 1 < a.N)
 #pragma unroll
-      for (int r = 0; r < RPT; ++r)
-        if (ok[r]) ck[(size_t)((n + 1) / CK) * d + row[r]] = acc[r][0];
+      for (int c = 0; c < CPW; ++c)
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+          if (ok[r]) ck[c][(size_t)((n + 1) / CK) * d + row[r]] = acc[r][c];
     if (a.ovt) {
-      // <phi_T|psi_{n+1}> of this column for the time-integrated infidelity
-      double o[2] = {0.0, 0.0};
+      // <phi_T|psi_{n+1}> of each column for the time-integrated infidelity
+      double o[2 * CPW];
+#pragma unroll
+      for (int q = 0; q < 2 * CPW; ++q) o[q] = 0.0;
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
-        if (ok[r]) {
-          const double2 t = a.tgt[col0 + row[r]];
-          const double pr = acc[r][0].re, pi = acc[r][0].im;
-          o[0] += t.x * pr + t.y * pi;
-          o[1] += t.x * pi - t.y * pr;
+        if (ok[r])
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            const double2 t = a.tgt[col0[c] + row[r]];
+            const double pr = acc[r][c].re, pi = acc[r][c].im;
+            o[2 * c + 0] += t.x * pr + t.y * pi;
+            o[2 * c + 1] += t.x * pi - t.y * pr;
+          }
+      block_sum<2 * CPW>(o, red);
+      if (tid == 0)
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          a.ovt[(((size_t)b * a.S + h + c) * a.N + n) * 2 + 0] = o[2 * c + 0];
+          a.ovt[(((size_t)b * a.S + h + c) * a.N + n) * 2 + 1] = o[2 * c + 1];
         }
-      block_sum<2>(o, red);
-      if (tid == 0) {
-        a.ovt[(((size_t)b * a.S + h) * a.N + n) * 2 + 0] = o[0];
-        a.ovt[(((size_t)b * a.S + h) * a.N + n) * 2 + 1] = o[1];
-      }
     }
   }
 
   C* psiN = reinterpret_cast<C*>(a.psiN);
-  double v[3] = {0.0, 0.0, pen};
+  // one column at a time: the reduction scratch holds at most 4 sums
 #pragma unroll
-  for (int r = 0; r < RPT; ++r)
-    if (ok[r]) {
-      psiN[col0 + row[r]] = acc[r][0];
-      const double2 t = a.tgt[col0 + row[r]];
-      const double pr = acc[r][0].re, pi = acc[r][0].im;
-      v[0] += t.x * pr + t.y * pi;  // Re conj(phi) psi
-      v[1] += t.x * pi - t.y * pr;  // Im conj(phi) psi
+  for (int c = 0; c < CPW; ++c) {
+    double v[3] = {0.0, 0.0, pen[c]};
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+      if (ok[r]) {
+        psiN[col0[c] + row[r]] = acc[r][c];
+        const double2 t = a.tgt[col0[c] + row[r]];
+        const double pr = acc[r][c].re, pi = acc[r][c].im;
+        v[0] += t.x * pr + t.y * pi;  // Re conj(phi) psi
+        v[1] += t.x * pi - t.y * pr;  // Im conj(phi) psi
+      }
+    block_sum<3>(v, red);
+    if (tid == 0) {
+      a.ovl[((size_t)b * a.S + h + c) * 2 + 0] = v[0];
+      a.ovl[((size_t)b * a.S + h + c) * 2 + 1] = v[1];
+      a.pen[(size_t)b * a.S + h + c] = v[2];
     }
-  block_sum<3>(v, red);
-  if (tid == 0) {
-    a.ovl[((size_t)b * a.S + h) * 2 + 0] = v[0];
-    a.ovl[((size_t)b * a.S + h) * 2 + 1] = v[1];
-    a.pen[(size_t)b * a.S + h] = v[2];
   }
 }
 

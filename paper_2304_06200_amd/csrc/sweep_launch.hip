@@ -214,6 +214,9 @@ bool sweep_supported(const DevOps& ops, int dim, int K, bool c128, size_t lds_li
   sh->threads = threads;
   sh->fwd_rows_per_thread = frpt;
   sh->fwd_threads = fthreads;
+  sh->fwd_cpw = 1;
+  // two columns per forward workgroup: complex64, 1024 threads, 1-2 rows each
+  sh->lds_fwd2 = (!c128 && wide && frpt <= 2) ? lds_bytes(2, flr, dim, ops.halo, cs) : 0;
   sh->groups = G;
   sh->lds_fwd = fwd;
   sh->lds_bwd = bwd_bytes(G);

@@ -48,6 +48,13 @@ hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream
       if (sh.fwd_rows_per_thread == 1) fk = hg_forward<R, 1, W, PU, kWideThreads, false>;
       else if (sh.fwd_rows_per_thread == 2) fk = hg_forward<R, 2, W, PU, kWideThreads, false>;
       else if constexpr (W <= 5) fk = hg_forward<R, 3, W, PU, kWideThreads, false>;
+      // two state columns per workgroup (complex64, 1-2 rows per thread)
+      if constexpr (sizeof(R) == 4 && (PU & 8) == 0) {
+        if (sh.fwd_cpw == 2) {
+          if (sh.fwd_rows_per_thread == 1) fk = hg_forward<R, 1, W, PU, kWideThreads, false, 2>;
+          else fk = hg_forward<R, 2, W, PU, kWideThreads, false, 2>;
+        }
+      }
     }
   }
   if constexpr (WK <= 2 && ((sizeof(R) == 4 && (RPT <= 2 || (RPT == 3 && W <= 5 && G <= 2))) ||
@@ -61,8 +68,9 @@ hipError_t run_sweep_kernels(const SweepArgs& a, const SweepShape& sh, hipStream
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds_bwd);
   if (e != hipSuccess) return e;
   const dim3 grid(sh.n_states, sh.n_batch), block(sh.threads), fblock(sh.fwd_threads);
+  const dim3 fgrid(sh.n_states / (sh.fwd_cpw > 1 ? sh.fwd_cpw : 1), sh.n_batch);
   if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(fk, grid, fblock, sh.lds_fwd, st, a);
+  hipLaunchKernelGGL(fk, fgrid, fblock, sh.lds_fwd, st, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.ovt && (e = launch_integrated(a, sh.n_batch, st)) != hipSuccess) return e;

@@ -132,6 +132,30 @@ def test_union_order_and_imaginary_diagonals(case):
         assert_parity(run(p, dt, prob=prob), ref, dt, label=case)
 
 
+@pytest.mark.parametrize("mode,w_int", [("reconstruct", 0.0), ("checkpoint", 0.6)])
+def test_two_columns_per_forward_workgroup(mode, w_int):
+    """A batch large enough that the complex64 forward runs two state columns
+    per workgroup (32 evaluations x 16 states at d = 640): every evaluation
+    bitwise equal to the same evaluation alone (one column per workgroup),
+    and one against the oracle."""
+    from workloads.configs import _amps
+    p = make_config("cfg3", N=4, d_c=40)
+    prob = make_problem(p)
+    U = np.stack([p.u] + [_amps(np.random.default_rng(300 + i), p.n_ctrl, p.n_steps)
+                          for i in range(31)])
+    kw = dict(mode=mode, ckpt_every=2 if mode == "checkpoint" else 0, w_int=w_int)
+    log(f"[case] two columns per forward workgroup, {mode}, w_int={w_int}")
+    rb = run(p, "c64", prob=prob, batch_u=U, **kw)
+    for i in (0, 17, 31):
+        r1 = run(p, "c64", prob=prob, batch_u=U[i:i + 1], **kw)
+        assert rb.cost[i] == r1.cost[0], i
+        assert np.array_equal(rb.grad[i].cpu().numpy(), r1.grad[0].cpu().numpy()), i
+    from oracle import grape
+    ref = grape.cost_and_grad(p.H0, p.Hk, U[17], p.dt, p.psi0, p.targets, omega=p.omega,
+                              w_fid=p.w_fid, w_pen=p.w_pen, w_int=w_int)
+    assert_parity(rb, ref, "c64", b=17, label="cpw2")
+
+
 def test_single_step_single_state_no_penalty():
     p = _cavity_problem(10, K=1, N=1, S=1, penalty=False)
     log("[case] N=1 S=1 K=1 no penalty")
