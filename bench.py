@@ -76,18 +76,21 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(batch):
     """HBM bytes per hg_backward launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (copy-calibrated), or None once the kernel sources differ
-    from the ones the counters were taken on."""
+    from the ones the counters were taken on, or for another batch size."""
     path = os.path.join(ROOT, "profiles", "hg_backward_cfg3_c64_hbm_bytes.md")
     try:
         txt = open(path).read()
     except OSError:
         return None
     vals = dict(l.split(": ", 1) for l in txt.splitlines()
-                if l.startswith(("traffic_bytes_per_launch:", "kernel_source_sha256_16:")))
+                if l.startswith(("traffic_bytes_per_launch:", "kernel_source_sha256_16:",
+                                 "concurrent_evals:")))
     if vals.get("kernel_source_sha256_16", "").strip() != kernel_source_hash():
+        return None
+    if vals.get("concurrent_evals", "").strip() != str(batch):
         return None
     return float(vals["traffic_bytes_per_launch"].strip())
 
@@ -292,7 +295,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--cpu-sample", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c128", action="store_true")
@@ -408,7 +411,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "hg_backward", "achieved": main_r["tflops_backward"],
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": main_r["tflops_backward"] / PEAK_VALU_TFLOPS,
-                     "traffic": measured_traffic() if B == 16 else None},
+                     "traffic": measured_traffic(B)},
     }
     if "c128" in out:
         c = out["c128"]

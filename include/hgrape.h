@@ -59,7 +59,10 @@ typedef enum {
   HG_ERR_UNSUPPORTED = 9            /* shape outside what the kernels are built for */
 } hg_status;
 
-typedef enum { HG_C64 = 0, HG_C128 = 1 } hg_dtype;  /* arithmetic of the Taylor products */
+/* Arithmetic of the Taylor products.  HG_C64: products in FP32; the state
+ * vectors the sweeps carry (psi, and Lambda backwards), norms, overlaps,
+ * penalty and reductions in FP64.  HG_C128: everything FP64. */
+typedef enum { HG_C64 = 0, HG_C128 = 1 } hg_dtype;
 typedef enum { HG_MODE_RECONSTRUCT = 0, HG_MODE_CHECKPOINT = 1 } hg_mode;
 /* Choice of (m, s) per step under the bound E_A(m, s) <= tau of App. C:
  * the paper's rule (smallest s, then smallest m; Sec. III.B) or the fewest

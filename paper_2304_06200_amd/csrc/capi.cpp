@@ -713,7 +713,7 @@ static Workspace layout(const hg_problem* p, int B, int N, int S_true, bool c128
   w.sched = take((size_t)2 * B * N * 4);
   const bool dn = p->dense;
   w.psiN = take(dn ? 0 : (size_t)B * S * d * cs);
-  w.cold = take(dn ? 0 : (size_t)B * S * Q * 3 * d * cs);
+  w.cold = take(dn ? 0 : (size_t)B * S * Q * 3 * d * 16);  // FP64 carried vectors
   const size_t C = ckpt_every > 0 ? (size_t)std::min(ckpt_every, N) : 0;
   const size_t nseg = ckpt_every > 0 ? ((size_t)N + ckpt_every - 1) / ckpt_every : 0;
   w.ckpt = take(dn ? 0 : (size_t)B * S * nseg * d * cs);

@@ -157,7 +157,7 @@ struct SweepBuffers {
   const double* psi0;              // [B][S][dim] complex128
   const double* targets;           // [B][S][dim] complex128
   void* psiN;                      // [B][S][dim] working precision
-  void* cold;                      // [B][S][3][dim] working precision
+  void* cold;                      // [B][S][Q][3][dim] complex FP64 (carried vectors)
   void* ckpt;                      // checkpoint variant: [B][S][ceil(N/C)][dim], else null
   void* segbuf;                    // checkpoint variant: [B][S][C][dim], else null
   double* ovl;                     // [B][S][2]

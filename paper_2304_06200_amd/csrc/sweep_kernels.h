@@ -34,6 +34,26 @@ struct alignas(2 * sizeof(R)) cx {
   R re, im;
 };
 
+// The vectors a sweep carries from term to term and step to step (psi, and
+// Lambda in the backward) accumulate in FP64 in both precisions; only the
+// copies that feed the next term's products are rounded to R.
+using CA = cx<double>;
+template <typename T, typename U>
+__device__ __forceinline__ cx<T> cxc(const cx<U>& x) {
+  return cx<T>{(T)x.re, (T)x.im};
+}
+// FP64 sums over the carried vectors are written as explicit FMA chains: the
+// compiler may not contract them differently in different kernel variants, so
+// a column gives bitwise the same norms and overlaps whichever variant runs it.
+__device__ __forceinline__ double acc_norm2(double s, CA z) {
+  return fma(z.im, z.im, fma(z.re, z.re, s));
+}
+// s + conj(t) z
+__device__ __forceinline__ void acc_dot(double& sr, double& si, double2 t, CA z) {
+  sr = fma(t.y, z.im, fma(t.x, z.re, sr));
+  si = fma(-t.y, z.re, fma(t.x, z.im, si));
+}
+
 struct SweepArgs {
   int d, K, N, S, W, halo, G, renorm_every;
   int ckpt_every;        // > 0: checkpointed-state variant, psi stored every ckpt_every steps
@@ -52,7 +72,7 @@ struct SweepArgs {
   const double2* psi0;   // [B][S][d]
   const double2* tgt;    // [B][S][d]
   void* psiN;            // [B][S][d] (working precision)
-  void* cold;            // [B][S][Q][3][d] (working precision; Q = gridDim.z of the backward)
+  void* cold;            // [B][S][Q][3][d] complex FP64 (Q = gridDim.z of the backward)
   void* ckpt;            // [B][S][ceil(N/C)][d] checkpoints psi_0, psi_C, ... (checkpoint variant)
   void* segbuf;          // [B][S][Q][C][d] states of the segment being swept back
   double* ovl;           // [B][S][2]
@@ -465,19 +485,22 @@ constexpr int kNotShared = -2;
 // Write the V accumulators of this thread's rows into buffer 0 of the block.
 // On a wave of the shared tail slab the last row carries only vector tv
 // (none if tv < 0), written on its own.
-template <typename R, int RPT, int V, int LR = RPT>
+template <typename R, int RPT, int V, int LR = RPT, typename A = R>
 __device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t (&rowb)[RPT],
                                             const bool (&ok)[RPT], int tv,
-                                            const cx<R> (&acc)[RPT][V]) {
+                                            const cx<A> (&acc)[RPT][V]) {
   using L = Blk<R, LR, V>;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     if (tv != kNotShared && r == RPT - 1) {
       if (tv >= 0 && ok[r]) {
-        cx<R> x = acc[r][0];
+        // select, then round: converting inside the selection makes the
+        // compiler index acc dynamically and move it to scratch memory
+        cx<A> y = acc[r][0];
 #pragma unroll
         for (int v = 1; v < V; ++v)
-          if (tv == v) x = acc[r][v];
+          if (tv == v) y = acc[r][v];
+        const cx<R> x = cxc<R>(y);
         lds_st(base + rowb[r] + (uint32_t)(tv / L::VP) * L::ps(d) + (uint32_t)(tv % L::VP) * L::CS, x);
       }
       continue;
@@ -487,7 +510,8 @@ __device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t
       for (int p = 0; p < L::NP; ++p) {
         typename L::Row w;
 #pragma unroll
-        for (int q = 0; q < L::VP; ++q) w.v[q] = (p * L::VP + q < V) ? acc[r][p * L::VP + q] : cx<R>{(R)0, (R)0};
+        for (int q = 0; q < L::VP; ++q)
+          w.v[q] = (p * L::VP + q < V) ? cxc<R>(acc[r][p * L::VP + q]) : cx<R>{(R)0, (R)0};
         lds_st(base + rowb[r] + p * L::ps(d), w);
       }
   }
@@ -505,13 +529,14 @@ __device__ __forceinline__ void block_store(uint32_t base, int d, const uint32_t
 // add of a per-row base (VGPR) and the diagonal's offset (SGPR); keeping all
 // RPT*W addresses in registers instead spills at these register budgets and
 // did not make the forward kernel faster.
-template <typename R, int RPT, int NR, int W, int PU, int V, int WK, bool AUX, bool SRC1, int LR = RPT>
+template <typename R, int RPT, int NR, int W, int PU, int V, int WK, bool AUX, bool SRC1, int LR = RPT,
+          typename A = R>
 __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, int g0,
                                             const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                             const cx<R> (&bv)[RPT][W],
                                             const cx<R> (&ek)[V][RPT][WK],
                                             const int (&cl)[RPT][W], const int (&ckl)[V][RPT][WK], R inv,
-                                            cx<R> (&acc)[RPT][V]) {
+                                            cx<A> (&acc)[RPT][V]) {
   using C = cx<R>;
   using L = Blk<R, LR, V>;
   using Row = typename L::Row;
@@ -584,13 +609,14 @@ __device__ __forceinline__ void taylor_term(uint32_t base, const SweepArgs& a, i
 
 // The shared tail slab's share of one Taylor term: vector VT of the last row
 // (RPT-1) only, with the same products as taylor_term for that vector.
-template <typename R, int RPT, int W, int PU, int V, int WK, bool AUX, bool SRC1, int VT, int LR>
+template <typename R, int RPT, int W, int PU, int V, int WK, bool AUX, bool SRC1, int VT, int LR,
+          typename A>
 __device__ __forceinline__ void tail_piece(uint32_t base, const SweepArgs& a, int g0,
                                            const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                            const cx<R> (&bv)[RPT][W],
                                            const cx<R> (&ek)[V][RPT][WK],
                                            const int (&cl)[RPT][W], const int (&ckl)[V][RPT][WK], R inv,
-                                           cx<R> (&acc)[RPT][V]) {
+                                           cx<A> (&acc)[RPT][V]) {
   using C = cx<R>;
   using L = Blk<R, LR, V>;
   constexpr int r = RPT - 1;
@@ -626,25 +652,25 @@ __device__ __forceinline__ void tail_piece(uint32_t base, const SweepArgs& a, in
   if (ok[r]) lds_st(rb + opaque_s(base + DST) + vo, t);
 }
 
-template <typename R, int RPT, int W, int PU, int V, int WK, bool AUX, bool SRC1, int LR>
+template <typename R, int RPT, int W, int PU, int V, int WK, bool AUX, bool SRC1, int LR, typename A>
 __device__ __forceinline__ void tail_share(int tv, uint32_t base, const SweepArgs& a, int g0,
                                            const uint32_t (&rowb)[RPT], const bool (&ok)[RPT],
                                            const cx<R> (&bv)[RPT][W],
                                            const cx<R> (&ek)[V][RPT][WK],
                                            const int (&cl)[RPT][W], const int (&ckl)[V][RPT][WK], R inv,
-                                           cx<R> (&acc)[RPT][V]) {
+                                           cx<A> (&acc)[RPT][V]) {
   switch (tv) {
     case 0:
-      tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 0, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
+      tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 0, LR, A>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
       break;
     case 1:
-      if constexpr (V > 1) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 1, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
+      if constexpr (V > 1) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 1, LR, A>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
       break;
     case 2:
-      if constexpr (V > 2) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 2, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
+      if constexpr (V > 2) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 2, LR, A>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
       break;
     case 3:
-      if constexpr (V > 3) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 3, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
+      if constexpr (V > 3) tail_piece<R, RPT, W, PU, V, WK, AUX, SRC1, 3, LR, A>(base, a, g0, rowb, ok, bv, ek, cl, ckl, inv, acc);
       break;
     default:
       break;
@@ -659,7 +685,7 @@ __device__ __forceinline__ void tail_share(int tv, uint32_t base, const SweepArg
 // `base` is the byte offset of buffer 0, plane 0, row 0.  The term loop is
 // unrolled by two so the buffer being read is a compile-time choice.  Ends
 // with a barrier, so the block may be rewritten right away.
-template <typename R, int RPT, int W, int PU, int V, int WK, bool AUX, int LR, bool SPLIT>
+template <typename R, int RPT, int W, int PU, int V, int WK, bool AUX, int LR, bool SPLIT, typename A>
 __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, int g0,
                                              const uint32_t (&rowb)[RPT],
                                              const bool (&ok)[RPT], const bool (&sv)[RPT],
@@ -668,7 +694,7 @@ __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, 
                                              const cx<R> (&ek)[V][RPT][WK],
                                              const int (&cl)[RPT][W], const int (&ckl)[V][RPT][WK],
                                              int m, int s, R sgn,
-                                             cx<R> (&acc)[RPT][V], XState& xs) {
+                                             cx<A> (&acc)[RPT][V], XState& xs) {
   // A wavefront whose last row slab lies past the dimension runs the RPT-1 row
   // variant (wave-uniform choice, both variants fully unrolled).  The waves of
   // a shared tail slab (tv != kNotShared: four waves on different SIMDs) run
@@ -679,25 +705,25 @@ __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, 
   constexpr int NRS = RPT > 1 ? RPT - 1 : 1;
   using BL = Blk<R, LR, V>;
   for (int l = 0; l < s; ++l) {
-    block_store<R, RPT, V, LR>(base, a.d, rowb, ok, tv, acc);
+    block_store<R, RPT, V, LR, A>(base, a.d, rowb, ok, tv, acc);
     __syncthreads();
     if constexpr (SPLIT) halo_exchange<R, LR, V>(a, base, 0u, xs);
     for (int j = 1; j <= m; j += 2) {
       const R i1 = sgn * lds_ld<R>(kInvOff + j * (int)sizeof(R));
       if (full)
-        taylor_term<R, RPT, RPT, W, PU, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i1, acc);
+        taylor_term<R, RPT, RPT, W, PU, V, WK, AUX, false, LR, A>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i1, acc);
       else
-        taylor_term<R, RPT, NRS, W, PU, V, WK, AUX, false, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i1, acc);
-      if (share) tail_share<R, RPT, W, PU, V, WK, AUX, false, LR>(tv, base, a, g0, rowb, ok, bv, ek, cl, ckl, i1, acc);
+        taylor_term<R, RPT, NRS, W, PU, V, WK, AUX, false, LR, A>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i1, acc);
+      if (share) tail_share<R, RPT, W, PU, V, WK, AUX, false, LR, A>(tv, base, a, g0, rowb, ok, bv, ek, cl, ckl, i1, acc);
       __syncthreads();
       if constexpr (SPLIT) halo_exchange<R, LR, V>(a, base, BL::bs(a.d), xs);
       if (j + 1 <= m) {
         const R i2 = sgn * lds_ld<R>(kInvOff + (j + 1) * (int)sizeof(R));
         if (full)
-          taylor_term<R, RPT, RPT, W, PU, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i2, acc);
+          taylor_term<R, RPT, RPT, W, PU, V, WK, AUX, true, LR, A>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i2, acc);
         else
-          taylor_term<R, RPT, NRS, W, PU, V, WK, AUX, true, LR>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i2, acc);
-        if (share) tail_share<R, RPT, W, PU, V, WK, AUX, true, LR>(tv, base, a, g0, rowb, ok, bv, ek, cl, ckl, i2, acc);
+          taylor_term<R, RPT, NRS, W, PU, V, WK, AUX, true, LR, A>(base, a, g0, rowb, ok, bv, ek, cl, ckl, i2, acc);
+        if (share) tail_share<R, RPT, W, PU, V, WK, AUX, true, LR, A>(tv, base, a, g0, rowb, ok, bv, ek, cl, ckl, i2, acc);
         __syncthreads();
         if constexpr (SPLIT) halo_exchange<R, LR, V>(a, base, 0u, xs);
       }
@@ -705,15 +731,15 @@ __device__ __forceinline__ void taylor_block(uint32_t base, const SweepArgs& a, 
   }
 }
 
-template <typename R, int RPT, bool SPLIT>
-__device__ __forceinline__ void renormalise(cx<R> (&p)[RPT], double* red, const SweepArgs& a,
+template <int RPT, bool SPLIT>
+__device__ __forceinline__ void renormalise(CA (&p)[RPT], double* red, const SweepArgs& a,
                                             XState& xs) {
   double nv[1] = {0.0};
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) nv[0] += (double)p[r].re * p[r].re + (double)p[r].im * p[r].im;
+  for (int r = 0; r < RPT; ++r) nv[0] = acc_norm2(nv[0], p[r]);
   block_sum<1>(nv, red);
   if constexpr (SPLIT) nv[0] = part_allsum(a, nv[0], xs, red);
-  const R sc = (R)(1.0 / sqrt(nv[0]));
+  const double sc = 1.0 / sqrt(nv[0]);
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     p[r].re *= sc;
@@ -759,7 +785,7 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
   uint32_t rowb[RPT];
   bool ok[RPT], sv[RPT];
   slab_valid<RPT>(d, sv);
-  C acc[RPT][CPW];
+  CA acc[RPT][CPW];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int i = tid + r * NT;
@@ -769,7 +795,7 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
       const double2 p = a.psi0[col0[c] + row[r]];
-      acc[r][c] = ok[r] ? C{(R)p.x, (R)p.y} : C{(R)0, (R)0};
+      acc[r][c] = ok[r] ? CA{p.x, p.y} : CA{0.0, 0.0};
     }
   }
   __syncthreads();
@@ -792,7 +818,7 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
     if (ck[c])
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
-        if (ok[r]) ck[c][row[r]] = acc[r][c];
+        if (ok[r]) ck[c][row[r]] = cxc<R>(acc[r][c]);
   }
   for (int n = 0; n < a.N; ++n) {
     const int m = a.msch[(size_t)b * a.N + n];
@@ -802,11 +828,11 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
     taylor_block<R, RPT, W, PU, CPW, 1, false, LR, SPLIT>(base, a, 0, rowb, ok, sv, kNotShared, bv,
                                                       ek, cl, ckf, m, s, (R)1, acc, xs);
     if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
-      if constexpr (CPW == 1) {
-        C p[RPT];
+      if constexpr (SPLIT) {
+        CA p[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) p[r] = acc[r][0];
-        renormalise<R, RPT, SPLIT>(p, red, a, xs);
+        renormalise<RPT, SPLIT>(p, red, a, xs);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) acc[r][0] = p[r];
       } else {
@@ -815,13 +841,12 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
         for (int c = 0; c < CPW; ++c) {
           nv[c] = 0.0;
 #pragma unroll
-          for (int r = 0; r < RPT; ++r)
-            nv[c] += (double)acc[r][c].re * acc[r][c].re + (double)acc[r][c].im * acc[r][c].im;
+          for (int r = 0; r < RPT; ++r) nv[c] = acc_norm2(nv[c], acc[r][c]);
         }
         block_sum<CPW>(nv, red);
 #pragma unroll
         for (int c = 0; c < CPW; ++c) {
-          const R sc = (R)(1.0 / sqrt(nv[c]));
+          const double sc = 1.0 / sqrt(nv[c]);
 #pragma unroll
           for (int r = 0; r < RPT; ++r) {
             acc[r][c].re *= sc;
@@ -836,15 +861,14 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
         if (ok[r])
 #pragma unroll
           for (int c = 0; c < CPW; ++c)
-            pen[c] += omega[row[r]] *
-                      ((double)acc[r][c].re * acc[r][c].re + (double)acc[r][c].im * acc[r][c].im);
+            pen[c] = fma(omega[row[r]], acc_norm2(0.0, acc[r][c]), pen[c]);
     }
     if (CK > 0 && (n + 1) % CK == 0 && n + 1 < a.N)
 #pragma unroll
       for (int c = 0; c < CPW; ++c)
 #pragma unroll
         for (int r = 0; r < RPT; ++r)
-          if (ok[r]) ck[c][(size_t)((n + 1) / CK) * d + row[r]] = acc[r][c];
+          if (ok[r]) ck[c][(size_t)((n + 1) / CK) * d + row[r]] = cxc<R>(acc[r][c]);
     if (a.ovt) {
       // <phi_T|psi_{n+1}> of each column for the time-integrated infidelity
       double o[2 * CPW];
@@ -855,10 +879,7 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
         if (ok[r])
 #pragma unroll
           for (int c = 0; c < CPW; ++c) {
-            const double2 t = a.tgt[col0[c] + row[r]];
-            const double pr = acc[r][c].re, pi = acc[r][c].im;
-            o[2 * c + 0] += t.x * pr + t.y * pi;
-            o[2 * c + 1] += t.x * pi - t.y * pr;
+            acc_dot(o[2 * c + 0], o[2 * c + 1], a.tgt[col0[c] + row[r]], acc[r][c]);
           }
       block_sum<2 * CPW>(o, red);
       if (tid == 0)
@@ -878,11 +899,8 @@ __global__ void __launch_bounds__(TPB) hg_forward(SweepArgs a) {
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
       if (ok[r]) {
-        psiN[col0[c] + row[r]] = acc[r][c];
-        const double2 t = a.tgt[col0[c] + row[r]];
-        const double pr = acc[r][c].re, pi = acc[r][c].im;
-        v[0] += t.x * pr + t.y * pi;  // Re conj(phi) psi
-        v[1] += t.x * pi - t.y * pr;  // Im conj(phi) psi
+        psiN[col0[c] + row[r]] = cxc<R>(acc[r][c]);
+        acc_dot(v[0], v[1], a.tgt[col0[c] + row[r]], acc[r][c]);  // conj(phi) psi
       }
     block_sum<3>(v, red);
     if (tid == 0) {
@@ -942,10 +960,10 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   // runs it.  Rarely touched per-row vectors and checkpoint segments are per
   // workgroup; only z = 0 writes the cost parts and the drift.
   const int z = blockIdx.z, Q = gridDim.z;
-  C* cold = reinterpret_cast<C*>(a.cold) + (((size_t)b * S + h) * Q + z) * 3 * d;
-  C* const c_psi = cold;          // psi_{n-1}
-  C* const c_lam = cold + d;      // propagated co-state
-  C* const c_cur = cold + 2 * d;  // Lambda_n (for the overlaps)
+  CA* cold = reinterpret_cast<CA*>(a.cold) + (((size_t)b * S + h) * Q + z) * 3 * d;
+  CA* const c_psi = cold;          // psi_{n-1}
+  CA* const c_lam = cold + d;      // propagated co-state
+  CA* const c_cur = cold + 2 * d;  // Lambda_n (for the overlaps)
 
   // Shared tail slab: the last plane of rows holds T slabs of 64 rows.  With
   // T = 4q+1 the last one (index ts = T-1) would leave one SIMD a slab more
@@ -967,7 +985,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   uint32_t rowb1[RPT], rowb2[RPT];
   bool ok[RPT], sv[RPT], own_psi[RPT], own_lam[RPT];
   slab_valid<RPT>(d, sv);
-  C pl[RPT][2];  // psi and Lambda
+  CA pl[RPT][2];  // psi and Lambda
   const C* psiN = reinterpret_cast<const C*>(a.psiN);
 
   // the turn: g, cost parts, Lambda_N = -(w_fid g/S) phi_T + (w_pen/(N S)) Omega psi_N
@@ -1009,9 +1027,9 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
     const C p = psiN[col0 + row[r]];
     const double2 t = a.tgt[col0 + row[r]];
     const double w = omega ? omega[row[r]] : 0.0;
-    pl[r][0] = own_psi[r] ? p : C{(R)0, (R)0};
-    pl[r][1].re = own_lam[r] ? (R)(fr * t.x - fi * t.y + cpen * w * (double)p.re) : (R)0;
-    pl[r][1].im = own_lam[r] ? (R)(fr * t.y + fi * t.x + cpen * w * (double)p.im) : (R)0;
+    pl[r][0] = own_psi[r] ? cxc<double>(p) : CA{0.0, 0.0};
+    pl[r][1].re = own_lam[r] ? fr * t.x - fi * t.y + cpen * w * (double)p.re : 0.0;
+    pl[r][1].im = own_lam[r] ? fr * t.y + fi * t.x + cpen * w * (double)p.im : 0.0;
   }
   __syncthreads();
   // tail vector of this wavefront in the phase-1 block, the phase-2 block and
@@ -1047,13 +1065,14 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   const int n0 = ckpt ? sg * CK : 0;
   const int n1 = ckpt ? (n0 + CK < N ? n0 + CK : N) : N;
   if (ckpt) {
-    C f[RPT][1];
+    CA f[RPT][1];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) f[r][0] = own_psi[r] ? ckb[(size_t)sg * d + row[r]] : C{(R)0, (R)0};
+    for (int r = 0; r < RPT; ++r)
+      f[r][0] = own_psi[r] ? cxc<double>(ckb[(size_t)sg * d + row[r]]) : CA{0.0, 0.0};
     for (int n = n0; n < n1; ++n) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
-        if (own_psi[r]) seg[(size_t)(n - n0) * d + opaque(row[r])] = f[r][0];
+        if (own_psi[r]) seg[(size_t)(n - n0) * d + opaque(row[r])] = cxc<R>(f[r][0]);
       const int m = a.msch[(size_t)b * N + n];
       const int s = a.ssch[(size_t)b * N + n];
       C bv[RPT][W];
@@ -1062,10 +1081,10 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       taylor_block<R, RPT, W, PU, 1, 1, false, LR, SPLIT>(basef, a, 0, rowbf, ok, sv, tvp, bv, ekf,
                                                       cl, ckf, m, s, (R)1, f, xs);
       if (a.renorm_every > 0 && (n + 1) % a.renorm_every == 0) {
-        C p[RPT];
+        CA p[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) p[r] = f[r][0];
-        renormalise<R, RPT, SPLIT>(p, red, a, xs);
+        renormalise<RPT, SPLIT>(p, red, a, xs);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) f[r][0] = p[r];
       }
@@ -1086,10 +1105,10 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       taylor_block<R, RPT, W, PU, 2, 1, false, LR, SPLIT>(base1, a, 0, rowb1, ok, sv, tv1, bv, ek1,
                                                       cl, ck1, m, s, (R)-1, pl, xs);
       if (a.renorm_every > 0 && n % a.renorm_every == 0) {
-        C p[RPT];
+        CA p[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) p[r] = pl[r][0];
-        renormalise<R, RPT, SPLIT>(p, red, a, xs);
+        renormalise<RPT, SPLIT>(p, red, a, xs);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) pl[r][0] = p[r];
       }
@@ -1101,7 +1120,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
       }
     } else {
       // phase 1 (checkpoint variant): Lambda alone; psi_{n-1} from the segment
-      C lm[RPT][1];
+      CA lm[RPT][1];
 #pragma unroll
       for (int r = 0; r < RPT; ++r) lm[r][0] = pl[r][1];
       C ekf[1][RPT][1];
@@ -1110,7 +1129,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
         const int i = opaque(row[r]);
-        if (own_psi[r]) c_psi[i] = seg[(size_t)(n - n0) * d + i];
+        if (own_psi[r]) c_psi[i] = cxc<double>(seg[(size_t)(n - n0) * d + i]);
         if (own_lam[r]) c_lam[i] = lm[r][0];
       }
     }
@@ -1131,7 +1150,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
         // Y starts from psi_{n-1}: on the shared tail only its psi owner
-        yx[r][0] = own_psi[r] ? c_psi[opaque(row[r])] : C{(R)0, (R)0};
+        yx[r][0] = own_psi[r] ? cxc<R>(c_psi[opaque(row[r])]) : C{(R)0, (R)0};
 #pragma unroll
         for (int v = 1; v < V2; ++v) yx[r][v] = C{(R)0, (R)0};
       }
@@ -1149,11 +1168,11 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
         if (ok[r]) {
-          const C lc = c_cur[opaque(row[r])];
+          const CA lc = c_cur[opaque(row[r])];
 #pragma unroll
           for (int v = 0; v < G; ++v)
-            gv[v] += rot[v] ? (double)lc.re * yx[r][v + 1].im - (double)lc.im * yx[r][v + 1].re
-                            : (double)lc.re * yx[r][v + 1].re + (double)lc.im * yx[r][v + 1].im;
+            gv[v] += rot[v] ? lc.re * yx[r][v + 1].im - lc.im * yx[r][v + 1].re
+                            : lc.re * yx[r][v + 1].re + lc.im * yx[r][v + 1].im;
         }
       block_sum<G>(gv, red);
       if (tid == 0)
@@ -1169,20 +1188,20 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int i = opaque(row[r]);
-      const C ps = ok[r] ? c_psi[i] : C{(R)0, (R)0};
-      pl[r][0] = own_psi[r] ? ps : C{(R)0, (R)0};
-      pl[r][1] = own_lam[r] ? c_lam[i] : C{(R)0, (R)0};
+      const CA ps = ok[r] ? c_psi[i] : CA{0.0, 0.0};
+      pl[r][0] = own_psi[r] ? ps : CA{0.0, 0.0};
+      pl[r][1] = own_lam[r] ? c_lam[i] : CA{0.0, 0.0};
       if (n >= 1 && own_lam[r] && (omega || a.ovt)) {
         const double w = omega ? cpen * omega[i] : 0.0;
-        double lr = (double)pl[r][1].re + w * (double)ps.re;
-        double li = (double)pl[r][1].im + w * (double)ps.im;
+        double lr = pl[r][1].re + w * ps.re;
+        double li = pl[r][1].im + w * ps.im;
         if (a.ovt) {
           const double2 t = a.tgt[col0 + i];
           lr += sgr * t.x - sgi * t.y;
           li += sgr * t.y + sgi * t.x;
         }
-        pl[r][1].re = (R)lr;
-        pl[r][1].im = (R)li;
+        pl[r][1].re = lr;
+        pl[r][1].im = li;
       }
     }
   }
@@ -1196,7 +1215,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   for (int r = 0; r < RPT; ++r)
     if (own_psi[r]) {
       const double2 p0 = a.psi0[col0 + row[r]];
-      const double dr = (double)pl[r][0].re - p0.x, di = (double)pl[r][0].im - p0.y;
+      const double dr = pl[r][0].re - p0.x, di = pl[r][0].im - p0.y;
       dv[0] += dr * dr + di * di;
     }
   block_sum<1>(dv, red);
