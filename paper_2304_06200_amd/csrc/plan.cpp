@@ -140,6 +140,8 @@ static int select_one_min_mu(double theta, int sigma, double tau, double u, int3
 
 namespace {
 
+bool near(double a, double b) { return b >= 0.0 && std::fabs(a - b) <= 1e-12 * std::max(a, b); }
+
 // Feasibility thresholds for fixed (sigma, tau, u): th[s][m] is the largest
 // norm theta with E_A(m, s, theta) <= tau (negative if none), found by
 // bisection on the same floating-point function the direct search uses.
@@ -152,6 +154,7 @@ struct Thresholds {
   double tau = 0.0, u = 0.0;
   std::vector<std::array<double, 61>> th;  // index s (1-based), m (1..60)
   std::vector<double> smax;                // max_m th[s][m]
+  std::vector<std::pair<double, int64_t>> sorted;  // every threshold >= 0 with its s, ascending
   int64_t s_lim = 0;
   bool capped = false;
 
@@ -194,7 +197,23 @@ struct Thresholds {
       }
       th.push_back(row);
       smax.push_back(mx);
+      const size_t old = sorted.size();
+      for (int m = 1; m <= 60; ++m)
+        if (row[m] >= 0.0) sorted.emplace_back(row[m], (int64_t)ss);
+      std::sort(sorted.begin() + old, sorted.end());
+      std::inplace_merge(sorted.begin(), sorted.begin() + old, sorted.end());
     }
+  }
+
+  // Is theta within rounding noise (near) of any threshold of rows 1..s_max?
+  // Every b with near(t, b) lies in [t (1 - 2e-12), t (1 + 2e-12)], so only
+  // that slice of the sorted thresholds is tested, with near() itself.
+  bool near_any(double t, int64_t s_max) const {
+    auto it = std::lower_bound(sorted.begin(), sorted.end(),
+                               std::make_pair(t * (1.0 - 2e-12), std::numeric_limits<int64_t>::min()));
+    for (; it != sorted.end() && it->first <= t * (1.0 + 2e-12); ++it)
+      if (it->second <= s_max && near(t, it->first)) return true;
+    return false;
   }
 };
 
@@ -217,8 +236,6 @@ std::shared_ptr<Thresholds> table_for(int sigma, double tau, double u) {
   g_tabs[key] = t;
   return t;
 }
-
-bool near(double a, double b) { return b >= 0.0 && std::fabs(a - b) <= 1e-12 * std::max(a, b); }
 
 }  // namespace
 
@@ -258,9 +275,10 @@ int plan_steps(const double* theta, int64_t n, int sigma, double tau, double u, 
           break;
         }
         tab->extend(s);
-        for (int m = 1; m <= 60; ++m)
-          if (near(t, tab->th[s][m])) exact = false;
-        if (!exact) break;
+        if (tab->near_any(t, s)) {
+          exact = false;
+          break;
+        }
         if (t <= tab->smax[s]) {
           int m = 1;
           while (m <= 60 && !(t <= tab->th[s][m])) ++m;
@@ -308,12 +326,7 @@ int plan_steps(const double* theta, int64_t n, int sigma, double tau, double u, 
       for (m = 1; m <= 60; ++m)
         if (t <= tab->th[s][m]) break;
       // decisions made close to a threshold are re-taken by the direct search
-      for (int64_t s2 = 1; s2 <= s && exact; ++s2)
-        for (int m2 = 1; m2 <= 60; ++m2)
-          if (near(t, tab->th[s2][m2])) {
-            exact = false;
-            break;
-          }
+      if (exact && tab->near_any(t, s)) exact = false;
     }
     if (exact) {
       m_out[i] = m;
