@@ -108,6 +108,9 @@ def test_planner_exact_at_thresholds():
     for t, sig in pts:
         mm, ss = _lib.hg_plan(np.array([t]), sig, 1e-12, 2.0 ** -53)
         assert (int(mm[0]), int(ss[0])) == oplan.select(float(t), sig, 1e-12), (t, sig)
+        # the fewest-products rule takes the same near-threshold fall-back
+        mm, ss = _lib.hg_plan_rule(np.array([t]), sig, 1e-12, 2.0 ** -53, _lib.HG_PLAN_MIN_MU)
+        assert (int(mm[0]), int(ss[0])) == oplan.select_min_mu(float(t), sig, 1e-12), (t, sig)
 
 
 def test_struct_layout_matches_header(tmp_path):
