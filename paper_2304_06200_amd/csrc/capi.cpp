@@ -989,13 +989,34 @@ static hg_status eval_core(hg_problem* p, const hg_eval_desc* d, hg_result* resu
     r.overlap_im = h_res[b * 8 + 4];
     int64_t mu = 0;
     double mt = 0.0, mb = 0.0, dr = 0.0;
+    // E_A(m, s, theta) grows with theta for fixed (m, s), so the largest bound
+    // is found by evaluating it once per (m, s) pair at the largest norm
+    // planned with that pair: a handful of evaluations instead of N (a fixed
+    // table, no allocation; pairs beyond it are evaluated step by step)
+    struct PairTop {
+      int32_t m, s;
+      double theta;
+    };
+    PairTop top[32];
+    int ntop = 0;
+    const double u53 = std::ldexp(1.0, -53);
     for (int n = 0; n < N; ++n) {
       const size_t i = (size_t)b * N + n;
       if (!use_diag) mu += (int64_t)h_m[i] * h_s[i];
       mt = std::max(mt, h_theta[i]);
-      if (!d->schedule && !use_diag)
-        mb = std::max(mb, error_bound(h_theta[i], h_m[i], h_s[i], p->sigma, std::ldexp(1.0, -53)));
+      if (!d->schedule && !use_diag) {
+        int q = 0;
+        while (q < ntop && (top[q].m != h_m[i] || top[q].s != h_s[i])) ++q;
+        if (q < ntop)
+          top[q].theta = std::max(top[q].theta, h_theta[i]);
+        else if (ntop < 32)
+          top[ntop++] = PairTop{h_m[i], h_s[i], h_theta[i]};
+        else
+          mb = std::max(mb, error_bound(h_theta[i], h_m[i], h_s[i], p->sigma, u53));
+      }
     }
+    for (int q = 0; q < ntop; ++q)
+      mb = std::max(mb, error_bound(top[q].theta, top[q].m, top[q].s, p->sigma, u53));
     for (int h = 0; h < S; ++h) {
       // a split column's parts hold disjoint rows: combine their partial drifts
       double d2 = 0.0;

@@ -6,19 +6,23 @@ import dataclasses
 import numpy as np
 import pytest
 
-from gpu_common import assert_parity, log, make_problem, run
+from gpu_common import assert_parity, device_inputs, log, make_problem, run
 from workloads.configs import serving_request
 
 pytestmark = pytest.mark.gpu
 
 
-def _schedule(p, rule, tau):
-    from oracle import planner
+def _sigma(p):
     import scipy.sparse as sp
     pat = abs(p.H0)
     for h in p.Hk:
         pat = pat + abs(h)
-    sigma = int(np.max(np.diff(sp.csr_matrix(pat).indptr)))
+    return int(np.max(np.diff(sp.csr_matrix(pat).indptr)))
+
+
+def _schedule(p, rule, tau):
+    from oracle import planner
+    sigma = _sigma(p)
     pick = planner.select_min_mu if rule == "min_mu" else planner.select
     out = np.zeros((2, p.n_steps), dtype=np.int32)
     for n in range(p.n_steps):
@@ -44,3 +48,14 @@ def test_min_mu_rule(dtype):
     r = run(p, dtype, rule="min_mu")
     assert int(r.sum_mu[0]) == int(np.sum(sched[0] * sched[1]))
     assert_parity(r, ref, dtype, label="min-mu")
+    # the largest E_A of the schedule, which the library evaluates once per
+    # (m, s) pair at the pair's largest norm, equals the maximum taken step by step
+    import paper_2304_06200_amd as hg
+    from paper_2304_06200_amd import _lib as L
+    sigma = _sigma(p)
+    u_dev, _, _ = device_inputs(p)
+    theta = hg.step_norms(make_problem(p), u_dev, p.dt).cpu().numpy()[0]
+    m, s = hg.plan(theta, sigma, p.tau, rule="min_mu")
+    per_step = max(L.hg_error_bound(float(t), int(a), int(b), sigma, 2.0 ** -53)
+                   for t, a, b in zip(theta, m, s))
+    assert r.max_bound[0] == per_step
