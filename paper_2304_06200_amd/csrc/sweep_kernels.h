@@ -963,7 +963,9 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
   CA* cold = reinterpret_cast<CA*>(a.cold) + (((size_t)b * S + h) * Q + z) * 3 * d;
   CA* const c_psi = cold;          // psi_{n-1}
   CA* const c_lam = cold + d;      // propagated co-state
-  CA* const c_cur = cold + 2 * d;  // Lambda_n (for the overlaps)
+  // Lambda_n for the overlaps, in the working precision: it is used for one
+  // step only, and the narrower copy keeps the per-step rows within the L2
+  C* const c_cur = reinterpret_cast<C*>(cold + 2 * d);
 
   // Shared tail slab: the last plane of rows holds T slabs of 64 rows.  With
   // T = 4q+1 the last one (index ts = T-1) would leave one SIMD a slab more
@@ -1098,7 +1100,7 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
     assemble_B<R, RPT, W>(a, vals, ub, n, row, ok, cs, bv);
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
-      if (own_lam[r]) c_cur[opaque(row[r])] = pl[r][1];
+      if (own_lam[r]) c_cur[opaque(row[r])] = cxc<R>(pl[r][1]);
 
     if (!ckpt) {
       // phase 1: psi and Lambda through (T_m(-B))^s together
@@ -1168,11 +1170,11 @@ __global__ void __launch_bounds__(TPB) hg_backward(SweepArgs a) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
         if (ok[r]) {
-          const CA lc = c_cur[opaque(row[r])];
+          const C lc = c_cur[opaque(row[r])];
 #pragma unroll
           for (int v = 0; v < G; ++v)
-            gv[v] += rot[v] ? lc.re * yx[r][v + 1].im - lc.im * yx[r][v + 1].re
-                            : lc.re * yx[r][v + 1].re + lc.im * yx[r][v + 1].im;
+            gv[v] += rot[v] ? (double)lc.re * yx[r][v + 1].im - (double)lc.im * yx[r][v + 1].re
+                            : (double)lc.re * yx[r][v + 1].re + (double)lc.im * yx[r][v + 1].im;
         }
       block_sum<G>(gv, red);
       if (tid == 0)
